@@ -1,0 +1,167 @@
+/*
+ * stiles.h -- C ABI of an MI355X (gfx950) FP64 library for the selected
+ * inversion of symmetric positive-definite band-plus-arrowhead matrices.
+ *
+ * Method: arXiv 2504.19171 ("GPU-Accelerated Parallel Selected Inversion for
+ * Structured Matrices Using sTiles"), Sec. III.  A = L L^T is factored on the
+ * band and arrow tiles (the sTiles tile Cholesky the paper builds on, whose
+ * kernels it names in Sec. III-F: POTRF/TRSM/SYRK/GEMM), and Sigma = A^{-1} is
+ * computed only on the tile pattern of L ("case 7" of Sec. III-B) by the
+ * two-phase backward recurrence of Sec. III-D (Phase 1: diagonal-tile inverse
+ * and TRMM of each tile row; Phase 2: LAUUM and GEMM accumulations from the
+ * bottom-right tile to the top-left one).  log det A = 2 sum_j log L_jj is
+ * returned with the factor (not in the paper).
+ *
+ * Conventions common to every call
+ * --------------------------------
+ * - All matrices are IEEE binary64.  Sizes are int64_t.
+ * - n is the total order, `arrow` (a) the number of dense trailing rows and
+ *   columns, nb = n - a the order of the band part, `bandwidth` (w) the
+ *   half-bandwidth of the band part in elements (w >= nb-1 means a dense band),
+ *   `tile` (b) the tile size.  Constraints: n >= 1, 0 <= a < n, w >= 0,
+ *   tile in {64, 128, 192, 256}, a <= 512.
+ * - Tile layout ("tiles" below), one buffer of stiles_layout.total_doubles
+ *   doubles, every tile column-major:
+ *     band tile (J+d, J), J < N = ceil(nb/b), 0 <= d <= B:  b x b, leading
+ *       dimension b, at off_band + (J*(B+1) + d) * b*b; B = min(ceil(w/b), N-1).
+ *       Tiles with J+d >= N exist and are kept zero.
+ *     arrow tile J (rows nb .. nb+a_p-1, tile column J):  a_p x b, leading
+ *       dimension a_p, at off_arrow + J * a_p*b; a_p = a rounded up to 16.
+ *     corner (rows and columns nb .. nb+a_p-1):  a_p x a_p, leading dimension
+ *       a_p, at off_corner.
+ *   Padding makes every tile full: band rows nb .. N*b-1 and arrow rows
+ *   a .. a_p-1 are identity on the diagonal and zero elsewhere.  This is exact:
+ *   Sigma on real indices and log det are unchanged (log 1 = 0).
+ * - Pointers named "device" are HIP device pointers; the caller allocates and
+ *   frees every buffer.  The library never retains or frees caller memory and
+ *   allocates nothing.
+ * - `stream` is a hipStream_t (NULL = the default stream).  Every call only
+ *   enqueues work on `stream` and returns; results are ready when the stream
+ *   is.  Calls on different streams may overlap if they use different buffers
+ *   and workspaces.
+ * - Return value: 0 when the work was enqueued; -i when argument i (1-based)
+ *   is invalid; STILES_EHIP when a HIP call failed.  Numerical outcomes are
+ *   reported in the device `info` word (see stiles_factor / stiles_selinv).
+ */
+#ifndef STILES_H
+#define STILES_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STILES_OK 0
+#define STILES_EHIP (-100)      /* a HIP runtime call failed */
+#define STILES_ETIMEOUT (-101)  /* a device wait on a tile-ready flag exceeded its spin limit */
+#define STILES_EBADL (-102)     /* stiles_selinv: a diagonal entry of L is not positive */
+#define STILES_ENOTBUILT (-103) /* reserved for bindings: library not loaded */
+
+typedef struct stiles_layout {
+    int64_t n, bandwidth, arrow; /* arguments as given */
+    int32_t tile;                /* b */
+    int32_t bt;                  /* B: tile half-bandwidth */
+    int64_t nb;                  /* n - arrow */
+    int64_t w;                   /* min(bandwidth, nb - 1) */
+    int64_t nt;                  /* N: band tile rows/columns */
+    int32_t arrow_ld;            /* a_p: arrow rounded up to 16 (0 when arrow == 0) */
+    int32_t reserved;
+    int64_t off_band, off_arrow, off_corner; /* offsets in doubles */
+    int64_t total_doubles;       /* size of one tile buffer in doubles */
+} stiles_layout;
+
+/*
+ * Fill *out with the tile layout of a matrix (host only, no GPU call).
+ * Returns 0, or -i for an invalid argument i.
+ */
+int stiles_layout_init(int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile,
+                       stiles_layout* out);
+
+/*
+ * Pack a matrix given in canonical band form (device memory, row-major) into
+ * the tile layout (device memory), writing every double of `tiles`:
+ *   ab     [(w+1) x nb]  ab[d*nb + j] = A[j+d][j], w = min(bandwidth, nb-1)
+ *   arrow_rows [a x nb]  arrow_rows[r*nb + j] = A[nb+r][j]  (NULL if a == 0)
+ *   corner [a x a]       corner[r*a + c] = A[nb+r][nb+c], full symmetric
+ *                        (NULL if a == 0)
+ * The paper stores the matrix in its "compressed tile format" shared with the
+ * Cholesky (Sec. III-B, selection step); this call builds this library's
+ * version of it.  Padding is written as described above.
+ */
+int stiles_pack(const double* ab, const double* arrow_rows, const double* corner,
+                double* tiles, int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile,
+                void* stream);
+
+/* Workspace sizes in bytes (host only). */
+size_t stiles_factor_workspace_bytes(const stiles_layout* lay);
+size_t stiles_selinv_workspace_bytes(const stiles_layout* lay);
+
+/*
+ * Tile Cholesky A = L L^T on the band and arrow tiles, and log det A.
+ *   A         device, tile layout, read only the lower triangles of diagonal
+ *             tiles and of the corner.
+ *   L         device, tile layout, output.  L may equal A (in place).  The
+ *             upper triangles of the diagonal tiles and the corner are set to
+ *             0; entries of band tiles outside the element band come out 0.
+ *   logdet    device, one double: 2 * sum_j log L_jj (NaN if not SPD).
+ *   info      device, one int32: 0 on success; k > 0 if the pivot of global
+ *             column k (1-based, k <= n) is not positive or is NaN, as in
+ *             LAPACK potrf -- L is then partly overwritten; STILES_ETIMEOUT if
+ *             a device wait exceeded its spin limit.
+ *   workspace device, at least stiles_factor_workspace_bytes(); contents on
+ *             entry are ignored.
+ * Defined by the problem statement of Sec. III (A SPD, A = L L^T) and the
+ * tile kernels named in Sec. III-F.
+ */
+int stiles_factor(const double* A, double* L, int64_t n, int64_t bandwidth, int64_t arrow,
+                  int32_t tile, double* logdet, int32_t* info, void* workspace,
+                  size_t workspace_bytes, void* stream);
+
+/*
+ * Selected inverse: Sigma = A^{-1} on the tile pattern of L (Sec. III-B,
+ * case 7), by Phase 1 and Phase 2 of Sec. III-D.
+ *   L         device, tile layout, a factor produced by stiles_factor (read only).
+ *   Sigma     device, tile layout, output: every band tile (J+d, J) with
+ *             J+d < N, every arrow tile and the corner hold Sigma; diagonal
+ *             tiles and the corner are full symmetric.  Must not alias L.
+ *   info      device, one int32: 0 on success; STILES_EBADL if a diagonal
+ *             entry of L is <= 0 or NaN; STILES_ETIMEOUT as above.
+ *   workspace device, at least stiles_selinv_workspace_bytes().
+ */
+int stiles_selinv(const double* L, double* Sigma, int64_t n, int64_t bandwidth, int64_t arrow,
+                  int32_t tile, int32_t* info, void* workspace, size_t workspace_bytes,
+                  void* stream);
+
+/*
+ * Per-kernel timing with HIP events (tracing support, not needed for results).
+ * While enabled, every kernel the library enqueues is bracketed by a pair of
+ * HIP events recorded on the same stream.  stiles_timing_collect() waits for
+ * the recorded events, adds their durations per kernel kind into
+ * ms[STILES_TK_COUNT] and launches[STILES_TK_COUNT] (host arrays, overwritten),
+ * releases the events and starts a new collection.  Enabling or disabling
+ * drops events not collected yet.  Thread-safe; costs two event records per
+ * launch while enabled.
+ */
+#define STILES_TK_POTRF 0      /* factor: diagonal tiles (POTRF, with their TRTRI) */
+#define STILES_TK_TRSM 1       /* factor: panel TRSM */
+#define STILES_TK_UPDATE 2     /* factor: trailing SYRK/GEMM updates */
+#define STILES_TK_PHASE1 3     /* selinv: Phase 1 (TRTRI, TRMM, LAUUM) */
+#define STILES_TK_SIGMA_OFF 4  /* selinv: Phase 2 off-diagonal GEMMs */
+#define STILES_TK_SIGMA_DIAG 5 /* selinv: Phase 2 diagonal updates */
+#define STILES_TK_OTHER 6      /* pack, copies, corner, finalization */
+#define STILES_TK_COUNT 7
+int stiles_timing_enable(int on);
+int stiles_timing_collect(double* ms, int64_t* launches);
+
+/* Static text for a return or info code. */
+const char* stiles_strerror(int code);
+
+/* Library version, major*10000 + minor*100 + patch. */
+int stiles_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* STILES_H */

@@ -1,0 +1,35 @@
+// Shared definitions of the HIP path: tile layout and small helpers.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+// Device-side view of the tile layout (see include/stiles.h for the format).
+struct Lay {
+    int64_t nb;        // order of the band part
+    int64_t w;         // half-bandwidth, clamped to nb-1
+    int64_t nt;        // N: band tile columns
+    int64_t off_band, off_arrow, off_corner, total;
+    int b;             // tile size
+    int bt;            // B: tile half-bandwidth
+    int ap;            // arrow rows rounded up to 16 (0 when there is no arrow)
+    int a;             // arrow rows
+
+    // Offset (in doubles) of band tile (J+d, J).
+    __host__ __device__ int64_t band(int64_t J, int d) const {
+        return off_band + (J * (int64_t)(bt + 1) + d) * (int64_t)b * b;
+    }
+    // Offset of arrow tile J (rows nb.., tile column J), a_p x b.
+    __host__ __device__ int64_t arrow(int64_t J) const { return off_arrow + J * (int64_t)ap * b; }
+    __host__ __device__ int64_t corner() const { return off_corner; }
+    // Number of band tiles below the diagonal in tile column J.
+    __host__ __device__ int s(int64_t J) const {
+        int64_t r = nt - 1 - J;
+        return (int)(r < bt ? r : bt);
+    }
+};
+
+// Row blocks of 64 rows in an arrow tile (a_p rows, last block may be partial).
+__host__ __device__ inline int arrow_blocks(int ap) { return (ap + 63) / 64; }
+__host__ __device__ inline int imin_(int x, int y) { return x < y ? x : y; }

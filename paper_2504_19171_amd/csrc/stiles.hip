@@ -1,0 +1,712 @@
+// HIP kernels and the C ABI (include/stiles.h) of the band-plus-arrowhead
+// selected inversion: tile Cholesky with log det, then Phase 1 and Phase 2 of
+// the two-phase backward recurrence (arXiv 2504.19171, Sec. III-D).
+//
+// Execution: every step is enqueued on the caller's stream; each kernel below
+// covers one tile-level operation over all the tiles it can do at once.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+#include <string.h>
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <vector>
+
+#include "../../include/stiles.h"
+#include "common.hpp"
+#include "gemm_block.hpp"
+#include "tile_ops.hpp"
+
+#define NT 256
+
+// ---------------------------------------------------------------------------
+// Layout
+// ---------------------------------------------------------------------------
+static int make_layout(int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile, stiles_layout* o) {
+    if (n < 1) return -1;
+    if (bandwidth < 0) return -2;
+    if (arrow < 0 || arrow >= n || arrow > 512) return -3;
+    if (!(tile == 64 || tile == 128 || tile == 192 || tile == 256)) return -4;
+    memset(o, 0, sizeof(*o));
+    o->n = n; o->bandwidth = bandwidth; o->arrow = arrow; o->tile = tile;
+    o->nb = n - arrow;
+    o->w = std::min<int64_t>(bandwidth, o->nb - 1);
+    o->nt = (o->nb + tile - 1) / tile;
+    int64_t bt = (o->w + tile - 1) / tile;
+    if (bt > o->nt - 1) bt = o->nt - 1;
+    o->bt = (int32_t)bt;
+    o->arrow_ld = (int32_t)((arrow + 15) / 16 * 16);
+    const int64_t b2 = (int64_t)tile * tile;
+    o->off_band = 0;
+    o->off_arrow = o->nt * (o->bt + 1) * b2;
+    o->off_corner = o->off_arrow + o->nt * (int64_t)o->arrow_ld * tile;
+    o->total_doubles = o->off_corner + (int64_t)o->arrow_ld * o->arrow_ld;
+    return 0;
+}
+
+static Lay to_dev(const stiles_layout& s) {
+    Lay l;
+    l.nb = s.nb; l.w = s.w; l.nt = s.nt;
+    l.off_band = s.off_band; l.off_arrow = s.off_arrow; l.off_corner = s.off_corner;
+    l.total = s.total_doubles;
+    l.b = s.tile; l.bt = s.bt; l.ap = s.arrow_ld; l.a = (int)s.arrow;
+    return l;
+}
+
+// ---------------------------------------------------------------------------
+// Small kernels
+// ---------------------------------------------------------------------------
+__global__ void k_set_int(int* p, int v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+// Pack the canonical band form into the tile layout (every double written).
+__global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, const double* __restrict__ P,
+                                            const double* __restrict__ C, double* __restrict__ T, Lay L) {
+    const int64_t b = L.b, b2 = b * b;
+    for (int64_t idx = blockIdx.x * (int64_t)NT + threadIdx.x; idx < L.total;
+         idx += (int64_t)gridDim.x * NT) {
+        double v = 0.0;
+        if (idx < L.off_arrow) {
+            const int64_t t = idx / b2, e = idx % b2;
+            const int64_t J = t / (L.bt + 1), d = t % (L.bt + 1);
+            const int64_t r = e % b, c = e / b;
+            const int64_t i = (J + d) * b + r, j = J * b + c;
+            if (J + d < L.nt) {
+                if (i < L.nb && j < L.nb) {
+                    const int64_t hi = i > j ? i : j, lo = i > j ? j : i;
+                    if (hi - lo <= L.w) v = ab[(hi - lo) * L.nb + lo];
+                } else if (i == j) {
+                    v = 1.0;
+                }
+            }
+        } else if (idx < L.off_corner) {
+            const int64_t e = idx - L.off_arrow;
+            const int64_t J = e / ((int64_t)L.ap * b), f = e % ((int64_t)L.ap * b);
+            const int64_t r = f % L.ap, c = f / L.ap;
+            const int64_t j = J * b + c;
+            if (r < L.a && j < L.nb) v = P[r * L.nb + j];
+        } else {
+            const int64_t e = idx - L.off_corner;
+            const int64_t r = e % L.ap, c = e / L.ap;
+            if (r < L.a && c < L.a) v = C[r * L.a + c];
+            else if (r == c) v = 1.0;
+        }
+        T[idx] = v;
+    }
+}
+
+// Zero the band tiles (J+d, J) with J+d >= N (outside the matrix).
+__global__ __launch_bounds__(NT) void k_zero_unused(double* T, Lay L) {
+    const int64_t b2 = (int64_t)L.b * L.b;
+    const int64_t ntail = (int64_t)L.bt * (L.bt + 1) / 2;  // tiles J+d >= N
+    const int64_t tot = ntail * b2;
+    for (int64_t idx = blockIdx.x * (int64_t)NT + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * NT) {
+        const int64_t t = idx / b2, e = idx % b2;
+        // enumerate (J, d) with J = N-1-m, d = m+1..B, m = 0..B-1
+        int64_t m = 0, cnt = t;
+        while (cnt >= L.bt - m) { cnt -= L.bt - m; ++m; }
+        const int64_t J = L.nt - 1 - m, d = m + 1 + cnt;
+        T[L.band(J, (int)d) + e] = 0.0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Factor kernels
+// ---------------------------------------------------------------------------
+
+// POTRF of one m x m diagonal block (m <= 256), optional TRTRI of the result
+// into X, log det partial into ldp[0..1], first failing column into *info
+// (atomicMin of the 1-based global column col_base + c + 1).
+__global__ __launch_bounds__(NT) void k_potrf(double* M, int64_t ld, int m, double* X, int64_t ldx,
+                                             double* ldp, int* info, int64_t col_base) {
+    extern __shared__ double smem[];
+    int fail;
+    double s, c;
+    potrf_tile(M, ld, m, smem, &fail, &s, &c);
+    if (threadIdx.x == 0) {
+        ldp[0] = s;
+        ldp[1] = c;
+        if (fail >= 0) atomicMin(info, (int)(col_base + fail + 1));
+    }
+    if (X) {
+        __syncthreads();
+        int bad;
+        trtri_tile(M, ld, X, ldx, m, smem, &bad);
+    }
+}
+
+// Rows of the panel below tile J (band tiles J+1..J+s, then the arrow tile),
+// one 64-row block per workgroup: C <- C * X^T with X = L_JJ^{-1} (TRSM).
+__device__ inline void panel_rows(const Lay& L, double* base, int64_t J, int blk, double*& C,
+                                  int64_t& ld, int& valid) {
+    const int nb64 = L.b / 64;
+    const int s = L.s(J);
+    if (blk < s * nb64) {
+        const int d = 1 + blk / nb64, rb = blk % nb64;
+        C = base + L.band(J, d) + rb * 64;
+        ld = L.b;
+        valid = 64;
+    } else {
+        const int rb = blk - s * nb64;
+        C = base + L.arrow(J) + rb * 64;
+        ld = L.ap;
+        valid = imin_(64, L.ap - rb * 64);
+    }
+}
+
+// In place: columns are produced last block first, so every column block
+// read later is still unmodified (X^T is upper triangular).
+__device__ inline void trsm_rows(double* C, int64_t ld, int valid, const double* X, int64_t ldx,
+                                 int ncols, double* smem) {
+    for (int cb = ncols / 64 - 1; cb >= 0; --cb) {
+        GAcc g;
+        gacc_zero(g);
+        gemm_acc(g, opnd(C, ld, 0, valid), opnd(X + cb * 64, ldx, 1, 64), (cb + 1) * 64, smem);
+        gemm_store(g, smem, 1.0, 0.0, nullptr, 0, C + (int64_t)cb * 64 * ld, ld, valid, 64);
+    }
+}
+
+__global__ __launch_bounds__(NT) void k_trsm_panel(double* Lm, Lay L, int64_t J, const double* X) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    double* C;
+    int64_t ld;
+    int valid;
+    panel_rows(L, Lm, J, blockIdx.x, C, ld, valid);
+    trsm_rows(C, ld, valid, X, L.b, L.b, smem);
+}
+
+// Generic TRSM on a contiguous row panel (used for the blocked corner).
+__global__ __launch_bounds__(NT) void k_trsm_generic(double* C, int64_t ld, int rows, const double* X,
+                                                    int64_t ldx, int ncols) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    const int rb = blockIdx.x;
+    trsm_rows(C + rb * 64, ld, imin_(64, rows - rb * 64), X, ldx, ncols, smem);
+}
+
+// Trailing update after tile column J (right-looking):
+//   band tiles (J+d, J+e), 1 <= e <= d <= s:  -= L_{J+d,J} L_{J+e,J}^T
+//   arrow tiles (A, J+e):                      -= L_{A,J}   L_{J+e,J}^T
+//   corner:                                    -= L_{A,J}   L_{A,J}^T
+// One 64 x 64 output block per workgroup; diagonal tiles and the corner only
+// get their lower blocks.
+__global__ __launch_bounds__(NT) void k_update(double* Lm, Lay L, int64_t J) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    const int nb64 = L.b / 64;
+    const int s = L.s(J);
+    const int nab = arrow_blocks(L.ap);
+    int t = blockIdx.x;
+    const double *Ap, *Bp;
+    int64_t lda, ldb, ldo;
+    int va = 64, vb = 64;
+    double* O;
+    // band pairs
+    for (int d = 1; d <= s; ++d) {
+        for (int e = 1; e <= d; ++e) {
+            const int cnt = (d == e) ? nb64 * (nb64 + 1) / 2 : nb64 * nb64;
+            if (t < cnt) {
+                int rb, cb;
+                if (d == e) tri_decode(t, rb, cb);
+                else { rb = t % nb64; cb = t / nb64; }
+                Ap = Lm + L.band(J, d) + rb * 64; lda = L.b;
+                Bp = Lm + L.band(J, e) + cb * 64; ldb = L.b;
+                O = Lm + L.band(J + e, d - e) + rb * 64 + (int64_t)cb * 64 * L.b; ldo = L.b;
+                goto run;
+            }
+            t -= cnt;
+        }
+    }
+    // arrow tiles
+    for (int e = 1; e <= s; ++e) {
+        const int cnt = nab * nb64;
+        if (t < cnt) {
+            const int rb = t % nab, cb = t / nab;
+            Ap = Lm + L.arrow(J) + rb * 64; lda = L.ap; va = imin_(64, L.ap - rb * 64);
+            Bp = Lm + L.band(J, e) + cb * 64; ldb = L.b;
+            O = Lm + L.arrow(J + e) + rb * 64 + (int64_t)cb * 64 * L.ap; ldo = L.ap;
+            goto run;
+        }
+        t -= cnt;
+    }
+    {   // corner (lower blocks)
+        int rb, cb;
+        tri_decode(t, rb, cb);
+        Ap = Lm + L.arrow(J) + rb * 64; lda = L.ap; va = imin_(64, L.ap - rb * 64);
+        Bp = Lm + L.arrow(J) + cb * 64; ldb = L.ap; vb = imin_(64, L.ap - cb * 64);
+        O = Lm + L.corner() + rb * 64 + (int64_t)cb * 64 * L.ap; ldo = L.ap;
+    }
+run:
+    GAcc g;
+    gacc_zero(g);
+    gemm_acc(g, opnd(Ap, lda, 0, va), opnd(Bp, ldb, 1, vb), L.b, smem);
+    gemm_store(g, smem, -1.0, 1.0, O, ldo, O, ldo, va, vb);
+}
+
+static int update_blocks(const Lay& L, int64_t J) {
+    const int nb64 = L.b / 64, s = L.s(J), nab = arrow_blocks(L.ap);
+    int cnt = 0;
+    for (int d = 1; d <= s; ++d)
+        for (int e = 1; e <= d; ++e) cnt += (d == e) ? nb64 * (nb64 + 1) / 2 : nb64 * nb64;
+    if (L.ap > 0) cnt += s * nab * nb64 + nab * (nab + 1) / 2;
+    return cnt;
+}
+
+// C (rows x rows, lower blocks) -= P P^T, P rows x K (generic, corner blocking).
+__global__ __launch_bounds__(NT) void k_syrk_generic(double* C, int64_t ldc, const double* P,
+                                                    int64_t ldp, int rows, int K) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    int rb, cb;
+    tri_decode(blockIdx.x, rb, cb);
+    const int va = imin_(64, rows - rb * 64), vb = imin_(64, rows - cb * 64);
+    GAcc g;
+    gacc_zero(g);
+    gemm_acc(g, opnd(P + rb * 64, ldp, 0, va), opnd(P + cb * 64, ldp, 1, vb), K, smem);
+    double* O = C + rb * 64 + (int64_t)cb * 64 * ldc;
+    gemm_store(g, smem, -1.0, 1.0, O, ldc, O, ldc, va, vb);
+}
+
+__global__ void k_zero_block(double* C, int64_t ld, int rows, int cols) {
+    for (int idx = threadIdx.x + blockIdx.x * blockDim.x; idx < rows * cols; idx += blockDim.x * gridDim.x)
+        C[(idx % rows) + (int64_t)(idx / rows) * ld] = 0.0;
+}
+
+// Final log det (Neumaier sum of the per-block partials, in order) and info.
+__global__ void k_factor_final(const double* ldp, int nparts, const int* info_ws, double* logdet,
+                               int* info) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0, c = 0.0;
+    for (int i = 0; i < nparts; ++i) {
+        neumaier(s, c, ldp[2 * i]);
+        neumaier(s, c, ldp[2 * i + 1]);
+    }
+    const int f = *info_ws;
+    *info = (f == 0x7fffffff) ? 0 : f;
+    *logdet = (f == 0x7fffffff) ? (s + c) : __builtin_nan("");
+}
+
+// ---------------------------------------------------------------------------
+// Selected-inversion kernels
+// ---------------------------------------------------------------------------
+
+// Phase 1, diagonal tiles: X_J = L_JJ^{-1} ("TRSM(L_ii^T, I)"), stored in the
+// diagonal slots of the workspace; the corner inverse likewise.
+__global__ __launch_bounds__(NT) void k_trtri_all(const double* Lm, double* W, Lay L, int* info) {
+    __shared__ double smem[TRTRI_SMEM_DOUBLES];
+    const int64_t J = blockIdx.x;
+    int bad;
+    if (J < L.nt) {
+        trtri_tile(Lm + L.band(J, 0), L.b, W + L.band(J, 0), L.b, L.b, smem, &bad);
+    } else {
+        trtri_tile(Lm + L.corner(), L.ap, W + L.corner(), L.ap, L.ap, smem, &bad);
+    }
+    if (threadIdx.x == 0 && bad) atomicExch(info, STILES_EBADL);
+}
+
+// Phase 1, off-diagonal tiles: Lhat_{k,J} = L_{k,J} X_J for the band tiles
+// k = J+1..J+s and the arrow tile ("TRMM").  Grid: (J, 64-row block, col block).
+__global__ __launch_bounds__(NT) void k_trmm_all(const double* Lm, double* W, Lay L) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    const int nb64 = L.b / 64;
+    const int nab = arrow_blocks(L.ap);
+    const int rows_max = L.bt * nb64 + nab;
+    const int64_t J = blockIdx.x / (rows_max * nb64);
+    const int r = (int)(blockIdx.x % (rows_max * nb64));
+    const int blk = r / nb64, cb = r % nb64;
+    const int s = L.s(J);
+    if (blk >= s * nb64 + nab) return;
+    double* Cw;
+    int64_t ld;
+    int valid;
+    panel_rows(L, W, J, blk, Cw, ld, valid);
+    const double* Cl = Lm + (Cw - W);
+    const double* X = W + L.band(J, 0);
+    const int k0 = cb * 64;
+    GAcc g;
+    gacc_zero(g);
+    gemm_acc(g, opnd(Cl + (int64_t)k0 * ld, ld, 0, valid), opnd(X + k0 + (int64_t)k0 * L.b, L.b, 0, 64),
+             L.b - k0, smem);
+    gemm_store(g, smem, 1.0, 0.0, nullptr, 0, Cw + (int64_t)k0 * ld, ld, valid, 64);
+}
+
+// Phase 2 initial value of each diagonal tile, "LAUUM": Sigma_JJ = X_J^T X_J
+// (and the corner Sigma_AA = X_A^T X_A, which is final).  Lower 64 x 64
+// blocks, mirrored so the tiles are full symmetric.
+__global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, Lay L) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    const int nb64 = L.b / 64;
+    const int nab = arrow_blocks(L.ap);
+    const int per = std::max(nb64 * (nb64 + 1) / 2, nab * (nab + 1) / 2);
+    const int64_t J = blockIdx.x / per;
+    const int t = blockIdx.x % per;
+    const double* X;
+    double* O;
+    int m;
+    int64_t ld;
+    if (J < L.nt) {
+        if (t >= nb64 * (nb64 + 1) / 2) return;
+        X = W + L.band(J, 0); O = S + L.band(J, 0); m = L.b; ld = L.b;
+    } else {
+        if (t >= nab * (nab + 1) / 2) return;
+        X = W + L.corner(); O = S + L.corner(); m = L.ap; ld = L.ap;
+    }
+    int rb, cb;
+    tri_decode(t, rb, cb);
+    const int k0 = rb * 64;
+    const int va = imin_(64, m - rb * 64), vb = imin_(64, m - cb * 64);
+    GAcc g;
+    gacc_zero(g);
+    gemm_acc(g, opnd(X + k0 + (int64_t)rb * 64 * ld, ld, 1, va), opnd(X + k0 + (int64_t)cb * 64 * ld, ld, 0, vb),
+             m - k0, smem);
+    gemm_store_sym(g, smem, 1.0, 0.0, nullptr, 0, O + rb * 64 + (int64_t)cb * 64 * ld,
+                   O + cb * 64 + (int64_t)rb * 64 * ld, ld, rb == cb, va, vb);
+}
+
+// Operand for Sigma_{rows of tile (J+d), cols of tile (J+e)} (d, e >= 1, or the
+// arrow when == ARW), restricted to the 64-row block rb of the row tile.
+#define ARW (-1)
+__device__ inline Opnd sigma_block(const Lay& L, const double* S, int64_t J, int d, int rb, int e) {
+    if (d != ARW && e != ARW) {
+        if (d > e) return opnd(S + L.band(J + e, d - e) + rb * 64, L.b, 0, 64);
+        if (d == e) return opnd(S + L.band(J + d, 0) + rb * 64, L.b, 0, 64);
+        return opnd(S + L.band(J + d, e - d) + (int64_t)rb * 64 * L.b, L.b, 1, 64);
+    }
+    if (d != ARW) return opnd(S + L.arrow(J + d) + (int64_t)rb * 64 * L.ap, L.ap, 1, 64);
+    const int va = imin_(64, L.ap - rb * 64);
+    if (e != ARW) return opnd(S + L.arrow(J + e) + rb * 64, L.ap, 0, va);
+    return opnd(S + L.corner() + rb * 64, L.ap, 0, va);
+}
+
+// Phase 2, off-diagonal tiles of column J ("GEMM" of Alg. 3):
+//   Sigma_{i,J} = - sum_{k in S(J)} Sigma_{i,k} Lhat_{k,J},  i in S(J)
+// S(J) = band tiles J+1..J+s and the arrow.  Sigma_{i,k} with i < k is read
+// as the transpose of the stored lower tile.
+__global__ __launch_bounds__(NT) void k_sigma_off(double* S, const double* W, Lay L, int64_t J) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    const int nb64 = L.b / 64;
+    const int s = L.s(J);
+    const int blk = blockIdx.x / nb64, cb = blockIdx.x % nb64;
+    int d, rb;
+    if (blk < s * nb64) { d = 1 + blk / nb64; rb = blk % nb64; }
+    else { d = ARW; rb = blk - s * nb64; }
+    const int vo = (d == ARW) ? imin_(64, L.ap - rb * 64) : 64;
+    GAcc g;
+    gacc_zero(g);
+    for (int e = 1; e <= s; ++e) {
+        gemm_acc(g, sigma_block(L, S, J, d, rb, e),
+                 opnd(W + L.band(J, e) + (int64_t)cb * 64 * L.b, L.b, 0, 64), L.b, smem);
+    }
+    if (L.ap > 0)
+        gemm_acc(g, sigma_block(L, S, J, d, rb, ARW),
+                 opnd(W + L.arrow(J) + (int64_t)cb * 64 * L.ap, L.ap, 0, 64), L.ap, smem);
+    double* O;
+    int64_t ldo;
+    if (d != ARW) { O = S + L.band(J, d) + rb * 64 + (int64_t)cb * 64 * L.b; ldo = L.b; }
+    else { O = S + L.arrow(J) + rb * 64 + (int64_t)cb * 64 * L.ap; ldo = L.ap; }
+    gemm_store(g, smem, -1.0, 0.0, nullptr, 0, O, ldo, vo, 64);
+}
+
+// Phase 2, diagonal tile of column J ("LAUUM" then "GEMM" of Alg. 3):
+//   Sigma_JJ = X_J^T X_J - sum_{k in S(J)} Lhat_{k,J}^T Sigma_{k,J}
+// Lower 64 x 64 blocks, mirrored.
+__global__ __launch_bounds__(NT) void k_sigma_diag(double* S, const double* W, Lay L, int64_t J) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    const int s = L.s(J);
+    int rb, cb;
+    tri_decode(blockIdx.x, rb, cb);
+    GAcc g;
+    gacc_zero(g);
+    for (int e = 1; e <= s; ++e) {
+        gemm_acc(g, opnd(W + L.band(J, e) + (int64_t)rb * 64 * L.b, L.b, 1, 64),
+                 opnd(S + L.band(J, e) + (int64_t)cb * 64 * L.b, L.b, 0, 64), L.b, smem);
+    }
+    if (L.ap > 0)
+        gemm_acc(g, opnd(W + L.arrow(J) + (int64_t)rb * 64 * L.ap, L.ap, 1, 64),
+                 opnd(S + L.arrow(J) + (int64_t)cb * 64 * L.ap, L.ap, 0, 64), L.ap, smem);
+    double* T = S + L.band(J, 0);
+    gemm_store_sym(g, smem, -1.0, 1.0, T + rb * 64 + (int64_t)cb * 64 * L.b, L.b,
+                   T + rb * 64 + (int64_t)cb * 64 * L.b, T + cb * 64 + (int64_t)rb * 64 * L.b, L.b,
+                   rb == cb, 64, 64);
+}
+
+__global__ void k_selinv_final(const int* info_ws, int* info) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *info = *info_ws;
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+#define WS_HEAD 256  // bytes reserved at the start of every workspace (info word)
+
+static inline hipStream_t S_(void* s) { return (hipStream_t)s; }
+
+#define HIPCHK(x)                              \
+    do {                                       \
+        if ((x) != hipSuccess) return STILES_EHIP; \
+    } while (0)
+#define LAUNCHCHK()                                       \
+    do {                                                  \
+        if (hipGetLastError() != hipSuccess) return STILES_EHIP; \
+    } while (0)
+
+
+// Optional per-kernel event timing (see stiles_timing_enable in stiles.h).
+struct EvRec {
+    hipEvent_t a, b;
+    int kind;
+};
+static std::mutex g_tmu;
+static std::atomic<bool> g_timing{false};
+static std::vector<EvRec> g_ev;
+
+static hipEvent_t tm_begin(hipStream_t st) {
+    if (!g_timing.load(std::memory_order_relaxed)) return nullptr;
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventRecord(e, st) != hipSuccess) {
+        (void)hipEventDestroy(e);
+        return nullptr;
+    }
+    return e;
+}
+
+static void tm_end(hipEvent_t a, int kind, hipStream_t st) {
+    if (!a) return;
+    hipEvent_t b;
+    if (hipEventCreate(&b) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return;
+    }
+    (void)hipEventRecord(b, st);
+    std::lock_guard<std::mutex> g(g_tmu);
+    g_ev.push_back({a, b, kind});
+}
+
+static void tm_drop() {
+    std::lock_guard<std::mutex> g(g_tmu);
+    for (auto& e : g_ev) {
+        (void)hipEventSynchronize(e.b);
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    g_ev.clear();
+}
+
+#define LAUNCH(kind, kern, grid, block, shm, st, ...)                           \
+    do {                                                                       \
+        hipEvent_t _tm = tm_begin(st);                                         \
+        hipLaunchKernelGGL(kern, grid, block, shm, st, __VA_ARGS__);           \
+        if (hipGetLastError() != hipSuccess) return STILES_EHIP;               \
+        tm_end(_tm, kind, st);                                                 \
+    } while (0)
+
+static int grid_for(int64_t work) {
+    int64_t g = (work + NT - 1) / NT;
+    if (g > 65536) g = 65536;
+    if (g < 1) g = 1;
+    return (int)g;
+}
+
+extern "C" {
+
+int stiles_version(void) { return 100; }
+
+int stiles_timing_enable(int on) {
+    tm_drop();
+    g_timing.store(on != 0);
+    return 0;
+}
+
+int stiles_timing_collect(double* ms, int64_t* launches) {
+    if (!ms) return -1;
+    if (!launches) return -2;
+    for (int k = 0; k < STILES_TK_COUNT; ++k) {
+        ms[k] = 0.0;
+        launches[k] = 0;
+    }
+    std::lock_guard<std::mutex> g(g_tmu);
+    int rc = 0;
+    for (auto& e : g_ev) {
+        float t = 0.0f;
+        if (hipEventSynchronize(e.b) != hipSuccess || hipEventElapsedTime(&t, e.a, e.b) != hipSuccess) rc = STILES_EHIP;
+        if (e.kind >= 0 && e.kind < STILES_TK_COUNT) {
+            ms[e.kind] += (double)t;
+            launches[e.kind] += 1;
+        }
+        (void)hipEventDestroy(e.a);
+        (void)hipEventDestroy(e.b);
+    }
+    g_ev.clear();
+    return rc;
+}
+
+
+const char* stiles_strerror(int code) {
+    if (code == 0) return "success";
+    if (code > 0) return "matrix is not positive definite (info = failing column, 1-based)";
+    switch (code) {
+        case -1: return "invalid argument 1";
+        case -2: return "invalid argument 2";
+        case -3: return "invalid argument 3";
+        case -4: return "invalid argument 4";
+        case -5: return "invalid argument 5";
+        case -6: return "invalid argument 6";
+        case -7: return "invalid argument 7";
+        case -8: return "invalid argument 8";
+        case -9: return "invalid argument 9";
+        case -10: return "invalid argument 10";
+        case -11: return "invalid argument 11";
+        case STILES_EHIP: return "HIP runtime error";
+        case STILES_ETIMEOUT: return "device wait exceeded its spin limit";
+        case STILES_EBADL: return "a diagonal entry of L is not positive";
+        case STILES_ENOTBUILT: return "library not built or not loaded";
+        default: return "invalid argument";
+    }
+}
+
+int stiles_layout_init(int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile, stiles_layout* out) {
+    if (!out) return -5;
+    return make_layout(n, bandwidth, arrow, tile, out);
+}
+
+size_t stiles_factor_workspace_bytes(const stiles_layout* lay) {
+    if (!lay) return 0;
+    // head + log det partials (N + 2 blocks) + one b x b inverse + the 256 x 256
+    // inverse of the blocked corner.
+    return WS_HEAD + sizeof(double) * (size_t)(2 * (lay->nt + 2)) +
+           sizeof(double) * (size_t)((int64_t)lay->tile * lay->tile + 256 * 256);
+}
+
+size_t stiles_selinv_workspace_bytes(const stiles_layout* lay) {
+    if (!lay) return 0;
+    return WS_HEAD + sizeof(double) * (size_t)lay->total_doubles;
+}
+
+int stiles_pack(const double* ab, const double* arrow_rows, const double* corner, double* tiles,
+                int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile, void* stream) {
+    stiles_layout lay;
+    int rc = make_layout(n, bandwidth, arrow, tile, &lay);
+    if (rc) return rc - 4;
+    if (!ab) return -1;
+    if (arrow > 0 && !arrow_rows) return -2;
+    if (arrow > 0 && !corner) return -3;
+    if (!tiles) return -4;
+    Lay L = to_dev(lay);
+    LAUNCH(STILES_TK_OTHER, k_pack, dim3(grid_for(L.total)), dim3(NT), 0, S_(stream), ab, arrow_rows, corner,
+                       tiles, L);
+    return 0;
+}
+
+int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile,
+                  double* logdet, int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
+    stiles_layout lay;
+    int rc = make_layout(n, bandwidth, arrow, tile, &lay);
+    if (rc) return rc - 2;
+    if (!A) return -1;
+    if (!Lm) return -2;
+    if (!logdet) return -7;
+    if (!info) return -8;
+    if (!workspace || workspace_bytes < stiles_factor_workspace_bytes(&lay)) return -9;
+    hipStream_t st = S_(stream);
+    Lay L = to_dev(lay);
+    char* ws = (char*)workspace;
+    int* winfo = (int*)ws;
+    double* ldp = (double*)(ws + WS_HEAD);
+    double* X = ldp + 2 * (L.nt + 2);
+    double* Xc = X + (int64_t)L.b * L.b;
+
+    if (A != Lm) {
+        hipEvent_t tm = tm_begin(st);
+        HIPCHK(hipMemcpyAsync(Lm, A, sizeof(double) * (size_t)L.total, hipMemcpyDeviceToDevice, st));
+        tm_end(tm, STILES_TK_OTHER, st);
+    }
+    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, winfo, 0x7fffffff);
+    const size_t potrf_smem_b = sizeof(double) * potrf_smem_doubles(L.b);
+    for (int64_t J = 0; J < L.nt; ++J) {
+        LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), potrf_smem_b, st, Lm + L.band(J, 0), (int64_t)L.b, L.b, X,
+                           (int64_t)L.b, ldp + 2 * J, winfo, J * (int64_t)L.b);
+        const int rows = L.s(J) * (L.b / 64) + arrow_blocks(L.ap);
+        if (rows > 0) {
+            LAUNCH(STILES_TK_TRSM, k_trsm_panel, dim3(rows), dim3(NT), 0, st, Lm, L, J, (const double*)X);
+        }
+        const int ub = update_blocks(L, J);
+        if (ub > 0) {
+            LAUNCH(STILES_TK_UPDATE, k_update, dim3(ub), dim3(NT), 0, st, Lm, L, J);
+        }
+    }
+    int nparts = (int)L.nt;
+    if (L.ap > 0) {
+        double* Cc = Lm + L.corner();
+        if (L.ap <= 256) {
+            LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), sizeof(double) * potrf_smem_doubles(L.ap), st, Cc,
+                               (int64_t)L.ap, L.ap, (double*)nullptr, (int64_t)0, ldp + 2 * L.nt, winfo, L.nb);
+            nparts += 1;
+        } else {
+            const int c2 = L.ap - 256;
+            LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), sizeof(double) * potrf_smem_doubles(256), st, Cc,
+                               (int64_t)L.ap, 256, Xc, (int64_t)256, ldp + 2 * L.nt, winfo, L.nb);
+            LAUNCH(STILES_TK_OTHER, k_trsm_generic, dim3((c2 + 63) / 64), dim3(NT), 0, st, Cc + 256, (int64_t)L.ap, c2,
+                               (const double*)Xc, (int64_t)256, 256);
+            const int nab2 = (c2 + 63) / 64;
+            LAUNCH(STILES_TK_OTHER, k_syrk_generic, dim3(nab2 * (nab2 + 1) / 2), dim3(NT), 0, st,
+                               Cc + 256 + (int64_t)256 * L.ap, (int64_t)L.ap, (const double*)(Cc + 256),
+                               (int64_t)L.ap, c2, 256);
+            LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), sizeof(double) * potrf_smem_doubles(c2), st,
+                               Cc + 256 + (int64_t)256 * L.ap, (int64_t)L.ap, c2, (double*)nullptr, (int64_t)0,
+                               ldp + 2 * (L.nt + 1), winfo, L.nb + 256);
+            LAUNCH(STILES_TK_OTHER, k_zero_block, dim3(64), dim3(NT), 0, st, Cc + (int64_t)256 * L.ap, (int64_t)L.ap,
+                               256, c2);
+            nparts += 2;
+        }
+    }
+    LAUNCH(STILES_TK_OTHER, k_factor_final, dim3(1), dim3(64), 0, st, (const double*)ldp, nparts, (const int*)winfo,
+                       logdet, (int*)info);
+    return 0;
+}
+
+int stiles_selinv(const double* Lm, double* S, int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile,
+                  int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
+    stiles_layout lay;
+    int rc = make_layout(n, bandwidth, arrow, tile, &lay);
+    if (rc) return rc - 2;
+    if (!Lm) return -1;
+    if (!S || S == Lm) return -2;
+    if (!info) return -7;
+    if (!workspace || workspace_bytes < stiles_selinv_workspace_bytes(&lay)) return -8;
+    hipStream_t st = S_(stream);
+    Lay L = to_dev(lay);
+    char* ws = (char*)workspace;
+    int* winfo = (int*)ws;
+    double* W = (double*)(ws + WS_HEAD);
+    const int nb64 = L.b / 64, nab = arrow_blocks(L.ap);
+
+    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, winfo, 0);
+    if (L.bt > 0) {
+        const int64_t tail = (int64_t)L.bt * (L.bt + 1) / 2 * L.b * L.b;
+        LAUNCH(STILES_TK_OTHER, k_zero_unused, dim3(grid_for(tail)), dim3(NT), 0, st, S, L);
+    }
+    // Phase 1
+    LAUNCH(STILES_TK_PHASE1, k_trtri_all, dim3((unsigned)(L.nt + (L.ap > 0))), dim3(NT), 0, st, Lm, W, L, winfo);
+    {
+        const int64_t g = L.nt * (int64_t)(L.bt * nb64 + nab) * nb64;
+        if (g > 0) {
+            LAUNCH(STILES_TK_PHASE1, k_trmm_all, dim3((unsigned)g), dim3(NT), 0, st, Lm, W, L);
+        }
+    }
+    {
+        const int per = std::max(nb64 * (nb64 + 1) / 2, nab * (nab + 1) / 2);
+        const int64_t g = (L.nt + (L.ap > 0)) * (int64_t)per;
+        LAUNCH(STILES_TK_PHASE1, k_lauum_all, dim3((unsigned)g), dim3(NT), 0, st, (const double*)W, S, L);
+    }
+    // Phase 2, bottom-right to top-left
+    for (int64_t J = L.nt - 1; J >= 0; --J) {
+        const int s = L.s(J);
+        const int rows = s * nb64 + nab;
+        if (rows == 0) continue;
+        LAUNCH(STILES_TK_SIGMA_OFF, k_sigma_off, dim3(rows * nb64), dim3(NT), 0, st, S, (const double*)W, L, J);
+        LAUNCH(STILES_TK_SIGMA_DIAG, k_sigma_diag, dim3(nb64 * (nb64 + 1) / 2), dim3(NT), 0, st, S, (const double*)W, L, J);
+    }
+    LAUNCH(STILES_TK_OTHER, k_selinv_final, dim3(1), dim3(64), 0, st, (const int*)winfo, (int*)info);
+    return 0;
+}
+
+}  // extern "C"

@@ -1,0 +1,224 @@
+"""Python binding of the C ABI in ``include/stiles.h`` (argument marshalling only).
+
+Every step of the factorization and of the selected inversion runs in the HIP
+kernels of ``libstiles.so``; PyTorch only provides device memory and the
+stream.  The library must have been built (``__graft_entry__.build()``):
+nothing here falls back to another implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import Optional, Tuple
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIBPATH = os.path.join(_HERE, "libstiles.so")
+
+_i64 = ctypes.c_int64
+_i32 = ctypes.c_int32
+_vp = ctypes.c_void_p
+_sz = ctypes.c_size_t
+
+STILES_EHIP = -100
+STILES_ETIMEOUT = -101
+STILES_EBADL = -102
+
+EXPORTED = (
+    "stiles_layout_init",
+    "stiles_pack",
+    "stiles_factor_workspace_bytes",
+    "stiles_selinv_workspace_bytes",
+    "stiles_factor",
+    "stiles_selinv",
+    "stiles_strerror",
+    "stiles_version",
+    "stiles_timing_enable",
+    "stiles_timing_collect",
+)
+
+TIMING_KINDS = ("potrf", "trsm", "update", "phase1", "sigma_off", "sigma_diag", "other")
+
+
+class _CLayout(ctypes.Structure):
+    _fields_ = [
+        ("n", _i64), ("bandwidth", _i64), ("arrow", _i64),
+        ("tile", _i32), ("bt", _i32),
+        ("nb", _i64), ("w", _i64), ("nt", _i64),
+        ("arrow_ld", _i32), ("reserved", _i32),
+        ("off_band", _i64), ("off_arrow", _i64), ("off_corner", _i64),
+        ("total_doubles", _i64),
+    ]
+
+
+_lib = None
+
+
+class StilesError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        super().__init__(f"{where}: {strerror(code)} ({code})")
+        self.code = code
+
+
+def load(path: Optional[str] = None):
+    """Load libstiles.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or LIBPATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with __graft_entry__.build()")
+    lib = ctypes.CDLL(p)
+    lib.stiles_layout_init.argtypes = [_i64, _i64, _i64, _i32, ctypes.POINTER(_CLayout)]
+    lib.stiles_layout_init.restype = ctypes.c_int
+    lib.stiles_pack.argtypes = [_vp, _vp, _vp, _vp, _i64, _i64, _i64, _i32, _vp]
+    lib.stiles_pack.restype = ctypes.c_int
+    lib.stiles_factor_workspace_bytes.argtypes = [ctypes.POINTER(_CLayout)]
+    lib.stiles_factor_workspace_bytes.restype = _sz
+    lib.stiles_selinv_workspace_bytes.argtypes = [ctypes.POINTER(_CLayout)]
+    lib.stiles_selinv_workspace_bytes.restype = _sz
+    lib.stiles_factor.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _vp, _sz, _vp]
+    lib.stiles_factor.restype = ctypes.c_int
+    lib.stiles_selinv.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _sz, _vp]
+    lib.stiles_selinv.restype = ctypes.c_int
+    lib.stiles_strerror.argtypes = [ctypes.c_int]
+    lib.stiles_strerror.restype = ctypes.c_char_p
+    lib.stiles_timing_enable.argtypes = [ctypes.c_int]
+    lib.stiles_timing_enable.restype = ctypes.c_int
+    lib.stiles_timing_collect.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(_i64)]
+    lib.stiles_timing_collect.restype = ctypes.c_int
+    lib.stiles_version.argtypes = []
+    lib.stiles_version.restype = ctypes.c_int
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def strerror(code: int) -> str:
+    return load().stiles_strerror(int(code)).decode()
+
+
+@dataclass(frozen=True)
+class Layout:
+    """Tile layout of one matrix (mirror of ``stiles_layout``)."""
+    n: int
+    bandwidth: int
+    arrow: int
+    tile: int
+    bt: int
+    nb: int
+    w: int
+    nt: int
+    arrow_ld: int
+    off_band: int
+    off_arrow: int
+    off_corner: int
+    total_doubles: int
+
+    def _c(self) -> _CLayout:
+        c = _CLayout()
+        rc = load().stiles_layout_init(self.n, self.bandwidth, self.arrow, self.tile, ctypes.byref(c))
+        assert rc == 0
+        return c
+
+    @property
+    def factor_workspace_bytes(self) -> int:
+        return int(load().stiles_factor_workspace_bytes(ctypes.byref(self._c())))
+
+    @property
+    def selinv_workspace_bytes(self) -> int:
+        return int(load().stiles_selinv_workspace_bytes(ctypes.byref(self._c())))
+
+
+def layout(n: int, bandwidth: int, arrow: int, tile: int) -> Layout:
+    c = _CLayout()
+    rc = load().stiles_layout_init(int(n), int(bandwidth), int(arrow), int(tile), ctypes.byref(c))
+    if rc != 0:
+        raise StilesError(rc, "stiles_layout_init")
+    return Layout(c.n, c.bandwidth, c.arrow, c.tile, c.bt, c.nb, c.w, c.nt, c.arrow_ld,
+                  c.off_band, c.off_arrow, c.off_corner, c.total_doubles)
+
+
+def _stream_handle(stream) -> int:
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _dev_f64(x, name: str):
+    import torch
+    if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 CUDA tensor")
+    return x
+
+
+def pack(ab, arrow_rows, corner, lay: Layout, out=None, stream=None):
+    """Pack device arrays in canonical band form into a new tile buffer."""
+    import torch
+    ab = _dev_f64(ab, "ab")
+    dev = ab.device
+    if out is None:
+        out = torch.empty(lay.total_doubles, dtype=torch.float64, device=dev)
+    P = _dev_f64(arrow_rows, "arrow_rows").data_ptr() if lay.arrow else None
+    C = _dev_f64(corner, "corner").data_ptr() if lay.arrow else None
+    rc = load().stiles_pack(ab.data_ptr(), P, C, out.data_ptr(), lay.n, lay.bandwidth, lay.arrow,
+                            lay.tile, _stream_handle(stream))
+    if rc != 0:
+        raise StilesError(rc, "stiles_pack")
+    return out
+
+
+def factor(A, lay: Layout, out=None, workspace=None, stream=None) -> Tuple[object, object, object]:
+    """Cholesky factor (tile layout) of A; returns (L, logdet, info) on the device.
+
+    ``out`` may be ``A`` itself (in place).  logdet is a 1-element float64
+    tensor and info a 1-element int32 tensor; neither is synchronised.
+    """
+    import torch
+    A = _dev_f64(A, "A")
+    dev = A.device
+    L = out if out is not None else torch.empty_like(A)
+    ws = workspace
+    if ws is None:
+        ws = torch.empty(lay.factor_workspace_bytes, dtype=torch.uint8, device=dev)
+    logdet = torch.empty(1, dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    rc = load().stiles_factor(A.data_ptr(), L.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                              logdet.data_ptr(), info.data_ptr(), ws.data_ptr(), ws.numel(),
+                              _stream_handle(stream))
+    if rc != 0:
+        raise StilesError(rc, "stiles_factor")
+    return L, logdet, info
+
+
+def selinv(L, lay: Layout, out=None, workspace=None, stream=None):
+    """Sigma = A^{-1} on the tile pattern of L; returns (Sigma, info) on the device."""
+    import torch
+    L = _dev_f64(L, "L")
+    dev = L.device
+    S = out if out is not None else torch.empty_like(L)
+    ws = workspace
+    if ws is None:
+        ws = torch.empty(lay.selinv_workspace_bytes, dtype=torch.uint8, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    rc = load().stiles_selinv(L.data_ptr(), S.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                              info.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    if rc != 0:
+        raise StilesError(rc, "stiles_selinv")
+    return S, info
+
+
+def timing_enable(on: bool = True) -> None:
+    """Bracket every library kernel launch with HIP events (per-kernel timing)."""
+    load().stiles_timing_enable(1 if on else 0)
+
+
+def timing_collect() -> dict:
+    """{kind: (total_ms, launches)} since the last collect (waits for the events)."""
+    n = len(TIMING_KINDS)
+    ms = (ctypes.c_double * n)()
+    cnt = (_i64 * n)()
+    rc = load().stiles_timing_collect(ms, cnt)
+    if rc != 0:
+        raise StilesError(rc, "stiles_timing_collect")
+    return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(TIMING_KINDS)}

@@ -1,0 +1,91 @@
+"""Helpers shared by the GPU tests: run the HIP path, compare with the oracle."""
+import math
+
+import numpy as np
+
+from paper_2504_19171_amd import inputs
+from paper_2504_19171_amd import layout as lo
+from paper_2504_19171_amd import stiles as st
+
+# Tolerances (stated for the hot path): Sigma entries within 1e-10 relative,
+# read on the correlation scale |dSigma_ij| / sqrt(Sigma_ii Sigma_jj) (and
+# plainly |dSigma_jj| / Sigma_jj on the diagonal); log det within 1e-12 of
+# sum_j |2 log L_jj|.  L is checked at 1e-12 of sqrt(A_ii) (row i of L has
+# norm sqrt(A_ii)).
+SIGMA_TOL = 1e-10
+LOGDET_TOL = 1e-12
+L_TOL = 1e-12
+
+
+def to_device(M, dev):
+    import torch
+    ab = torch.from_numpy(np.ascontiguousarray(M.ab)).to(dev)
+    P = torch.from_numpy(np.ascontiguousarray(M.P)).to(dev) if M.a else None
+    C = torch.from_numpy(np.ascontiguousarray(M.C)).to(dev) if M.a else None
+    return ab, P, C
+
+
+def run_gpu(M, b, dev="cuda:0"):
+    """pack -> factor -> selinv on the GPU; returns numpy tile buffers and scalars."""
+    import torch
+    lay = st.layout(M.n, M.w, M.a, b)
+    ab, P, C = to_device(M, dev)
+    A = st.pack(ab, P, C, lay)
+    L, logdet, info = st.factor(A, lay)
+    S, sinfo = st.selinv(L, lay)
+    torch.cuda.synchronize()
+    return dict(lay=lay, A=A.cpu().numpy(), L=L.cpu().numpy(), S=S.cpu().numpy(),
+                logdet=float(logdet.item()), info=int(info.item()), sinfo=int(sinfo.item()))
+
+
+def factor_error(Lt, lay, f, M):
+    """max |dL_ij| / sqrt(A_ii) over the band, arrow and corner; and the largest
+    entry of the band tiles that lies outside the element band (must be 0)."""
+    w = f.w
+    nb, a = lay.nb, lay.arrow
+    maxd = (lay.bt + 1) * lay.tile - 1
+    D = lo.band_part(Lt, lay, maxd)
+    sq = np.sqrt(np.concatenate([M.ab[0], np.diag(M.C)])) if a else np.sqrt(M.ab[0])
+    err = 0.0
+    for d in range(w + 1):
+        j = np.arange(nb - d)
+        ref = f.Lr[j + d, w - d]
+        err = max(err, float(np.max(np.abs(D[d, : nb - d] - ref) / sq[j + d])) if nb - d > 0 else 0.0)
+    outside = float(np.max(np.abs(D[w + 1:]))) if D.shape[0] > w + 1 else 0.0
+    if a:
+        LP = lo.arrow_part(Lt, lay)
+        err = max(err, float(np.max(np.abs(LP - f.LP) / sq[nb:, None])))
+        LC = lo.corner_part(Lt, lay)
+        err = max(err, float(np.max(np.abs(np.tril(LC) - f.LC) / sq[nb:, None])))
+        outside = max(outside, float(np.max(np.abs(np.triu(LC, 1)))))
+    return err, outside
+
+
+def sigma_error(St, lay, S):
+    """Correlation-scaled max error of Sigma on the pattern, and the max
+    relative error of the diagonal."""
+    nb, a = lay.nb, lay.arrow
+    D = lo.band_part(St, lay, S.Sb.shape[0] - 1)
+    dg = np.concatenate([S.Sb[0], np.diag(S.SC)]) if a else S.Sb[0]
+    sq = np.sqrt(dg)
+    err = 0.0
+    for d in range(S.Sb.shape[0]):
+        if nb - d <= 0:
+            break
+        j = np.arange(nb - d)
+        err = max(err, float(np.max(np.abs(D[d, : nb - d] - S.Sb[d, : nb - d]) / (sq[j] * sq[j + d]))))
+    diag_rel = float(np.max(np.abs(D[0] - S.Sb[0]) / S.Sb[0]))
+    if a:
+        SP = lo.arrow_part(St, lay)
+        err = max(err, float(np.max(np.abs(SP - S.SP) / np.outer(sq[nb:], sq[:nb]))))
+        SC = lo.corner_part(St, lay)
+        err = max(err, float(np.max(np.abs(SC - S.SC) / np.outer(sq[nb:], sq[nb:]))))
+        diag_rel = max(diag_rel, float(np.max(np.abs(np.diag(SC) - np.diag(S.SC)) / np.diag(S.SC))))
+        asym = float(np.max(np.abs(SC - SC.T)))
+        assert asym == 0.0, "corner not stored symmetric"
+    return err, diag_rel
+
+
+def logdet_error(logdet, f):
+    # scale: sum_j |2 log L_jj| (= |log det| when every pivot is >= 1), floored at 1
+    return abs(logdet - f.logdet) / max(1.0, float(np.sum(np.abs(2.0 * np.log(f.diag())))))

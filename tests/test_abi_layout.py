@@ -1,0 +1,96 @@
+"""Host-only checks of the C ABI and of the tile layout (no GPU calls)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2504_19171_amd import inputs
+from paper_2504_19171_amd import layout as lo
+from paper_2504_19171_amd import stiles as st
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    txt = open(os.path.join(ROOT, "include", "stiles.h")).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(stiles_\w+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_function():
+    lib = st.load()
+    names = header_functions()
+    assert set(names) == set(st.EXPORTED)
+    for name in names:
+        assert hasattr(lib, name), name
+    assert lib.stiles_version() >= 100
+
+
+@pytest.mark.parametrize("n,w,a,b", [(2020, 32, 20, 64), (100100, 1024, 100, 256), (60, 10, 5, 64),
+                                     (1000, 5000, 0, 128), (777, 100, 33, 192), (513, 0, 1, 256)])
+def test_layout_formula(n, w, a, b):
+    lay = st.layout(n, w, a, b)
+    nb = n - a
+    N = -(-nb // b)
+    we = min(w, nb - 1)
+    B = min(-(-we // b), N - 1)
+    ap = -(-a // 16) * 16
+    assert (lay.nb, lay.w, lay.nt, lay.bt, lay.arrow_ld) == (nb, we, N, B, ap)
+    assert lay.off_arrow == N * (B + 1) * b * b
+    assert lay.off_corner == lay.off_arrow + N * ap * b
+    assert lay.total_doubles == lay.off_corner + ap * ap
+    assert lay.selinv_workspace_bytes >= 8 * lay.total_doubles
+    assert lay.factor_workspace_bytes >= 8 * b * b
+
+
+@pytest.mark.parametrize("args,code", [((0, 1, 0, 64), -1), ((10, -1, 0, 64), -2), ((10, 1, 10, 64), -3),
+                                       ((10, 1, -1, 64), -3), ((1000, 1, 513, 64), -3), ((10, 1, 0, 32), -4),
+                                       ((10, 1, 0, 100), -4)])
+def test_layout_rejects_bad_arguments(args, code):
+    c = st._CLayout()
+    assert st.load().stiles_layout_init(*args, ctypes.byref(c)) == code
+
+
+def test_entry_points_reject_bad_arguments_before_any_gpu_call():
+    lib = st.load()
+    lay = st.layout(100, 4, 3, 64)
+    ws = lay.factor_workspace_bytes
+    # null A / L / logdet / info / workspace, too small workspace, bad sizes
+    assert lib.stiles_factor(None, 8, 100, 4, 3, 64, 8, 8, 8, ws, None) == -1
+    assert lib.stiles_factor(8, None, 100, 4, 3, 64, 8, 8, 8, ws, None) == -2
+    assert lib.stiles_factor(8, 8, 0, 4, 3, 64, 8, 8, 8, ws, None) == -3
+    assert lib.stiles_factor(8, 8, 100, 4, 3, 48, 8, 8, 8, ws, None) == -6
+    assert lib.stiles_factor(8, 8, 100, 4, 3, 64, None, 8, 8, ws, None) == -7
+    assert lib.stiles_factor(8, 8, 100, 4, 3, 64, 8, None, 8, ws, None) == -8
+    assert lib.stiles_factor(8, 8, 100, 4, 3, 64, 8, 8, 8, ws - 1, None) == -9
+    wss = lay.selinv_workspace_bytes
+    assert lib.stiles_selinv(None, 16, 100, 4, 3, 64, 8, 8, wss, None) == -1
+    assert lib.stiles_selinv(8, 8, 100, 4, 3, 64, 8, 8, wss, None) == -2   # Sigma aliases L
+    assert lib.stiles_selinv(8, 16, 100, 4, 3, 64, None, 8, wss, None) == -7
+    assert lib.stiles_selinv(8, 16, 100, 4, 3, 64, 8, 8, wss - 1, None) == -8
+    assert lib.stiles_pack(None, 8, 8, 8, 100, 4, 3, 64, None) == -1
+    assert lib.stiles_pack(8, None, 8, 8, 100, 4, 3, 64, None) == -2
+    assert lib.stiles_pack(8, 8, 8, 8, 100, 4, 3, 40, None) == -8
+    for code in (0, 5, -1, -100, -101, -102, -103):
+        assert st.strerror(code)
+
+
+@pytest.mark.parametrize("nb,w,a,b", [(200, 20, 7, 64), (60, 10, 5, 64), (300, 299, 0, 64), (130, 0, 17, 128)])
+def test_host_pack_roundtrip(nb, w, a, b):
+    M = inputs.arrowhead_spd(nb, w, a, seed=1)
+    lay = st.layout(M.n, w, a, b)
+    T = lo.host_pack(M.ab, M.P, M.C, lay)
+    D = lo.band_part(T, lay, lay.w)
+    we = lay.w
+    for d in range(we + 1):
+        np.testing.assert_array_equal(D[d, : nb - d], M.ab[d, : nb - d])
+    np.testing.assert_array_equal(lo.arrow_part(T, lay), M.P)
+    np.testing.assert_array_equal(lo.corner_part(T, lay), M.C)
+    # identity padding: pad diagonal 1, the rest of the pad 0
+    full = lo.band_tile(T, lay, lay.nt - 1, 0)
+    r0 = nb - (lay.nt - 1) * b
+    pad = full[r0:, r0:]
+    np.testing.assert_array_equal(pad, np.eye(b - r0))
+    assert np.all(full[r0:, :r0] == 0) and np.all(full[:r0, r0:] == 0)

@@ -1,0 +1,145 @@
+"""Parity of the HIP path with the oracle, element by element, on seeded
+inputs that span several tiles and a ragged tail, plus the edge cases."""
+import math
+
+import numpy as np
+import pytest
+
+from paper_2504_19171_amd import inputs
+from paper_2504_19171_amd import layout as lo
+
+pytestmark = pytest.mark.gpu
+
+CASES = [
+    # (nb, w, a, b)
+    (2000, 32, 20, 64),     # the small workload: n = 2,000 + 20, w = 32, tile 64
+    (1000, 0, 0, 64),       # diagonal matrix
+    (500, 499, 0, 64),      # dense band: B = N - 1
+    (60, 10, 5, 64),        # nb < b: a single band tile
+    (777, 100, 33, 128),    # ragged last tile, B = 1
+    (1300, 300, 0, 256),    # no arrow, tile 256, B = 2
+    (900, 64, 300, 64),     # arrow wider than 256: blocked corner
+    (513, 130, 1, 192),     # tile 192, one arrow row
+    (700, 200, 512, 64),    # widest arrow
+    (1100, 700, 45, 256),   # B = 3 of N = 5
+]
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    assert torch.cuda.is_available(), "no HIP device"
+    from paper_2504_19171_amd import stiles as st
+    st.load()
+    return torch
+
+
+@pytest.mark.parametrize("nb,w,a,b", CASES)
+def test_pack_is_bit_exact(torch_cuda, nb, w, a, b):
+    from gpu_util import to_device
+    from paper_2504_19171_amd import stiles as st
+    M = inputs.arrowhead_spd(nb, w, a, seed=nb + w)
+    lay = st.layout(M.n, w, a, b)
+    print(f"pack nb={nb} w={w} a={a} b={b}", flush=True)
+    T = st.pack(*to_device(M, "cuda:0"), lay).cpu().numpy()
+    np.testing.assert_array_equal(T, lo.host_pack(M.ab, M.P, M.C, lay))
+
+
+@pytest.mark.parametrize("nb,w,a,b", CASES)
+def test_factor_and_selinv_match_oracle(torch_cuda, oracle_mod, nb, w, a, b):
+    from gpu_util import run_gpu, factor_error, sigma_error, logdet_error, SIGMA_TOL, LOGDET_TOL, L_TOL
+    M = inputs.arrowhead_spd(nb, w, a, seed=1000 + nb)
+    print(f"parity nb={nb} w={w} a={a} b={b}", flush=True)
+    r = run_gpu(M, b)
+    assert r["info"] == 0 and r["sinfo"] == 0
+    f = oracle_mod.cholesky(M.ab, M.P, M.C)
+    S = oracle_mod.selinv(f, b)
+    lerr, outside = factor_error(r["L"], r["lay"], f, M)
+    serr, drel = sigma_error(r["S"], r["lay"], S)
+    lderr = logdet_error(r["logdet"], f)
+    print(f"  L err {lerr:.2e} (outside band {outside:.1e}), Sigma err {serr:.2e}, diag {drel:.2e}, "
+          f"logdet {lderr:.2e}", flush=True)
+    assert lerr <= L_TOL
+    assert outside == 0.0
+    assert serr <= SIGMA_TOL and drel <= SIGMA_TOL
+    assert lderr <= LOGDET_TOL
+
+
+def test_unused_tiles_and_padding(torch_cuda, oracle_mod):
+    """Band tiles beyond the matrix stay 0; pad rows of Sigma are identity."""
+    from gpu_util import run_gpu
+    nb, w, a, b = 777, 100, 33, 128
+    M = inputs.arrowhead_spd(nb, w, a, seed=5)
+    r = run_gpu(M, b)
+    lay = r["lay"]
+    S = r["S"]
+    for J in range(lay.nt):
+        for d in range(lay.bt + 1):
+            if J + d >= lay.nt:
+                assert np.all(lo.band_tile(S, lay, J, d) == 0.0)
+    last = lo.band_tile(S, lay, lay.nt - 1, 0)
+    r0 = nb - (lay.nt - 1) * b
+    np.testing.assert_array_equal(last[r0:, r0:], np.eye(b - r0))
+    np.testing.assert_array_equal(last[r0:, :r0], 0.0)
+    # the diagonal tiles of Sigma are stored full symmetric
+    for J in range(lay.nt):
+        t = lo.band_tile(S, lay, J, 0)
+        np.testing.assert_array_equal(t, t.T)
+
+
+@pytest.mark.parametrize("col", [0, 777, 1999, 2005])
+def test_not_positive_definite_info(torch_cuda, oracle_mod, col):
+    import torch
+    from gpu_util import to_device
+    from paper_2504_19171_amd import stiles as st
+    nb, w, a, b = 2000, 32, 20, 64
+    M = inputs.arrowhead_spd(nb, w, a, seed=3)
+    if col < nb:
+        M.ab[0, col] = -1.0
+    else:
+        M.C[col - nb, col - nb] = -1.0
+    f = oracle_mod.cholesky(M.ab, M.P, M.C)
+    assert f.info == col + 1
+    lay = st.layout(M.n, w, a, b)
+    print(f"not-SPD column {col}", flush=True)
+    A = st.pack(*to_device(M, "cuda:0"), lay)
+    L, logdet, info = st.factor(A, lay)
+    torch.cuda.synchronize()
+    assert int(info.item()) == col + 1
+    assert math.isnan(float(logdet.item()))
+
+
+def test_selinv_rejects_bad_L(torch_cuda):
+    import torch
+    from gpu_util import to_device
+    from paper_2504_19171_amd import stiles as st
+    M = inputs.arrowhead_spd(300, 20, 4, seed=2)
+    lay = st.layout(M.n, 20, 4, 64)
+    A = st.pack(*to_device(M, "cuda:0"), lay)
+    L, _, info = st.factor(A, lay)
+    # zero one diagonal entry of L (tile 2, local column 5)
+    off = lay.off_band + (2 * (lay.bt + 1)) * 64 * 64 + 5 * 64 + 5
+    L[off] = 0.0
+    S, sinfo = st.selinv(L, lay)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    assert int(sinfo.item()) == st.STILES_EBADL
+
+
+def test_bitwise_repeatable_and_in_place(torch_cuda):
+    import torch
+    from gpu_util import to_device
+    from paper_2504_19171_amd import stiles as st
+    M = inputs.arrowhead_spd(2000, 32, 20, seed=0)
+    lay = st.layout(M.n, 32, 20, 64)
+    A = st.pack(*to_device(M, "cuda:0"), lay)
+    L1, ld1, _ = st.factor(A, lay)
+    S1, _ = st.selinv(L1, lay)
+    L2, ld2, _ = st.factor(A, lay)
+    S2, _ = st.selinv(L2, lay)
+    A3 = A.clone()
+    L3, ld3, _ = st.factor(A3, lay, out=A3)   # in place
+    torch.cuda.synchronize()
+    assert torch.equal(L1, L2) and torch.equal(S1, S2)
+    assert torch.equal(L1, L3)
+    assert float(ld1.item()) == float(ld2.item()) == float(ld3.item())
