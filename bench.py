@@ -28,7 +28,7 @@ def kernel_flops(nb, w, a, b):
     """Algorithmic flops per step for each timing kind of the library."""
     from paper_2504_19171_amd import flops as fl
     N, B = fl._halfband(nb, w, b)
-    k = dict(potrf=0.0, trsm=0.0, update=0.0, phase1=0.0, sigma_off=0.0, sigma_diag=0.0, other=0.0)
+    k = dict(potrf=0.0, trsm=0.0, update=0.0, phase1=0.0, phase2=0.0, factor=0.0, other=0.0)
     for J in range(N):
         s = min(B, N - 1 - J)
         m = s * b + a
@@ -36,8 +36,7 @@ def kernel_flops(nb, w, a, b):
         k["trsm"] += m * b * b
         k["update"] += m * m * b
         k["phase1"] += b ** 3 / 3 + m * b * b + b ** 3 / 3
-        k["sigma_off"] += 2 * m * m * b
-        k["sigma_diag"] += m * b * b
+        k["phase2"] += 2 * m * m * b + m * b * b
     k["other"] += a ** 3 / 3          # corner factor
     k["phase1"] += 2 * a ** 3 / 3     # corner TRTRI + LAUUM
     return k

@@ -148,8 +148,8 @@ int stiles_selinv(const double* L, double* Sigma, int64_t n, int64_t bandwidth, 
 #define STILES_TK_TRSM 1       /* factor: panel TRSM */
 #define STILES_TK_UPDATE 2     /* factor: trailing SYRK/GEMM updates */
 #define STILES_TK_PHASE1 3     /* selinv: Phase 1 (TRTRI, TRMM, LAUUM) */
-#define STILES_TK_SIGMA_OFF 4  /* selinv: Phase 2 off-diagonal GEMMs */
-#define STILES_TK_SIGMA_DIAG 5 /* selinv: Phase 2 diagonal updates */
+#define STILES_TK_PHASE2 4     /* selinv: Phase 2 (persistent kernel) */
+#define STILES_TK_FACTOR 5     /* factor: persistent kernel */
 #define STILES_TK_OTHER 6      /* pack, copies, corner, finalization */
 #define STILES_TK_COUNT 7
 int stiles_timing_enable(int on);

@@ -33,3 +33,21 @@ struct Lay {
 // Row blocks of 64 rows in an arrow tile (a_p rows, last block may be partial).
 __host__ __device__ inline int arrow_blocks(int ap) { return (ap + 63) / 64; }
 __host__ __device__ inline int imin_(int x, int y) { return x < y ? x : y; }
+
+// The same pointer in every lane, held in scalar registers: lets loads use a
+// scalar base plus a 32-bit per-lane offset instead of 64-bit addresses.
+__device__ inline const double* uniform_ptr(const double* p) {
+    const uint64_t v = (uint64_t)p;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (const double*)(((uint64_t)hi << 32) | lo);
+}
+
+// Device-coherent load / store of one double (agent-scope relaxed atomics:
+// they bypass the non-coherent cache levels, see persist.hpp).
+__device__ inline double ld_coh(const double* p) {
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void st_coh(double* p, double v) {
+    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}

@@ -60,21 +60,21 @@ __device__ inline void gb_fetch(const Opnd& o, int k0, double r[4], bool a_side)
     // For the B operand the roles of "normal" and "transposed" swap: B(k, j)
     // normal is p[k + j*ld], i.e. contiguous along k like a transposed A.
     const int contig_x = a_side ? !o.trans : o.trans;
+    // offsets stay inside one operand tile (< 2^31 doubles)
+    const double* b = uniform_ptr(o.p);
+    const int ldi = (int)o.ld;
     if (contig_x) {
         const int x = t & 63;
         const bool ok = x < o.valid;
+        const int off = x + (k0 + (t >> 6)) * ldi;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = (t >> 6) + 4 * q;
-            r[q] = ok ? o.p[x + (int64_t)(k0 + k) * o.ld] : 0.0;
-        }
+        for (int q = 0; q < 4; ++q) r[q] = ok ? b[off + 4 * q * ldi] : 0.0;
     } else {
         const int k = t & 15;
+        const int x0 = t >> 4;
+        const int off = (k0 + k) + x0 * ldi;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int x = (t >> 4) + 16 * q;
-            r[q] = (x < o.valid) ? o.p[(k0 + k) + (int64_t)x * o.ld] : 0.0;
-        }
+        for (int q = 0; q < 4; ++q) r[q] = (x0 + 16 * q < o.valid) ? b[off + 16 * q * ldi] : 0.0;
     }
 }
 

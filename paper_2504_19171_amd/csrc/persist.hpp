@@ -1,0 +1,107 @@
+// Device-side task scheduling for persistent kernels.
+//
+// A persistent kernel is launched with a fixed number of workgroups; each one
+// repeatedly takes the next ticket from a global counter and runs the task
+// with that number.  Tickets follow a topological order of the task graph
+// (every task depends only on tasks with smaller tickets), so a task that
+// waits is always waiting for work that a running workgroup already owns:
+// the scheme cannot deadlock, whether or not all workgroups are resident.
+//
+// Dependencies are counters in device memory: a producer adds 1 once its
+// output is written; a consumer spins until the counter reaches the number of
+// producers it needs.  Every wait is bounded by a wall-clock limit; on expiry
+// the kernel records STILES_ETIMEOUT in the shared error word and every
+// workgroup leaves.
+//
+// Coherence without cache-wide fences.  On gfx950 an agent-scope release is a
+// write-back of the whole L2 of the XCD and an agent-scope acquire an
+// invalidation of it; with hundreds of workgroups doing one per task these
+// serialize (measured: ~15-35 us per release, and L2 re-reads falling from
+// TB/s to tens of GB/s).  So data handed between workgroups of one
+// persistent kernel never goes through the non-coherent caches instead: it is
+// stored with device-coherent (agent-scope relaxed atomic, "sc1") stores and
+// read with device-coherent loads (ld_coh / st_coh below).  A producer waits
+// for its stores to complete (s_waitcnt) in every wavefront, meets the other
+// wavefronts at a barrier, and only then bumps the counter; a consumer reads
+// the counter with a device-coherent load and meets its wavefronts at a
+// barrier before any of them loads the data.  Data written by earlier kernels
+// on the stream is read with ordinary loads.
+#pragma once
+#include "common.hpp"
+#include "../../include/stiles.h"
+
+struct Sched {
+    int* ticket;      // next ticket
+    int* err;         // 0, or an error code (all workgroups stop)
+    int64_t spin_limit;   // wall_clock64() ticks a wait may last
+    int withhold;     // ticket whose completion is never signalled (-1: none); test hook
+};
+
+// Thread 0 takes a ticket; broadcast to the workgroup.  Returns -1 when the
+// kernel is done or stopped.
+__device__ inline int sched_next(const Sched& s, int ntasks, int* sh) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = -1;
+        if (__hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+            t = __hip_atomic_fetch_add(s.ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (t >= ntasks) t = -1;
+        }
+        *sh = t;
+    }
+    __syncthreads();
+    // uniform across the workgroup: keep it (and all that derives from it) in
+    // scalar registers
+    return __builtin_amdgcn_readfirstlane(*sh);
+}
+
+// Wait until *flag >= target (thread 0 polls), then acquire for every thread.
+// Returns false if the kernel must stop (timeout or an error elsewhere).
+__device__ inline bool sched_wait(const Sched& s, int* flag, int target, int* sh) {
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            const int64_t t0 = wall_clock64();
+            while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (__hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+                if (wall_clock64() - t0 > s.spin_limit) {
+                    int zero = 0;
+                    __hip_atomic_compare_exchange_strong(s.err, &zero, STILES_ETIMEOUT, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        *sh = ok;
+    }
+    __syncthreads();
+    const bool ok = __builtin_amdgcn_readfirstlane(*sh) != 0;
+    __syncthreads();   // every thread has read *sh before it can be reused
+    return ok;
+}
+
+// Add 1 to *flag once every store of this workgroup (device-coherent) has
+// completed.
+__device__ inline void sched_signal(const Sched& s, int* flag, int ticket) {
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (threadIdx.x == 0 && ticket != s.withhold)
+        __hip_atomic_fetch_add(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Optional task tracing, compiled in with -DSTILES_TASK_TRACE (diagnostics
+// builds only): per task, wall-clock ticks at dequeue, after its waits and
+// after its signal, plus its kind / tile column / workgroup.
+#ifdef STILES_TASK_TRACE
+#define STILES_TRACE_MAX (1 << 20)
+#define STILES_TRACE_SLOTS 8
+__device__ unsigned long long g_trace[STILES_TRACE_SLOTS * STILES_TRACE_MAX];
+__device__ inline void trace_rec(int t, int slot, unsigned long long v) {
+    if (threadIdx.x == 0 && t >= 0 && t < STILES_TRACE_MAX) g_trace[STILES_TRACE_SLOTS * t + slot] = v;
+}
+#define TRACE(t, slot, v) trace_rec((t), (slot), (unsigned long long)(v))
+#else
+#define TRACE(t, slot, v) ((void)0)
+#endif

@@ -6,6 +6,7 @@
 // covers one tile-level operation over all the tiles it can do at once.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 #include <algorithm>
 #include <atomic>
@@ -16,6 +17,8 @@
 #include "common.hpp"
 #include "gemm_block.hpp"
 #include "tile_ops.hpp"
+#include "persist.hpp"
+#include "wave_gemm.hpp"
 
 #define NT 256
 
@@ -361,75 +364,287 @@ __global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, La
                    O + cb * 64 + (int64_t)rb * 64 * ld, ld, rb == cb, va, vb);
 }
 
-// Operand for Sigma_{rows of tile (J+d), cols of tile (J+e)} (d, e >= 1, or the
-// arrow when == ARW), restricted to the 64-row block rb of the row tile.
-#define ARW (-1)
-__device__ inline Opnd sigma_block(const Lay& L, const double* S, int64_t J, int d, int rb, int e) {
-    if (d != ARW && e != ARW) {
-        if (d > e) return opnd(S + L.band(J + e, d - e) + rb * 64, L.b, 0, 64);
-        if (d == e) return opnd(S + L.band(J + d, 0) + rb * 64, L.b, 0, 64);
-        return opnd(S + L.band(J + d, e - d) + (int64_t)rb * 64 * L.b, L.b, 1, 64);
-    }
-    if (d != ARW) return opnd(S + L.arrow(J + d) + (int64_t)rb * 64 * L.ap, L.ap, 1, 64);
-    const int va = imin_(64, L.ap - rb * 64);
-    if (e != ARW) return opnd(S + L.arrow(J + e) + rb * 64, L.ap, 0, va);
-    return opnd(S + L.corner() + rb * 64, L.ap, 0, va);
+#define ARW (-1)   // "the arrow" in place of a band tile offset
+
+// ---------------------------------------------------------------------------
+// Phase 2 as one persistent kernel
+// ---------------------------------------------------------------------------
+// Tile column J needs the off-diagonal tiles S(J) x S(J) of Sigma, where
+// S(J) = band tiles J+1..J+s and the arrow.  Everything in S(J) x S(J) except
+// what involves tile J+1 is final once column J+2 is done, so each output is
+// split into an "early" part (k over the far tiles J+2..J+s and the arrow),
+// which can start two columns ahead, and a "late" part (k = J+1).  Every task
+// is a 32 x 32 block whose reduction is spread over the 4 wavefronts of a
+// workgroup, so that the tasks on the dependency chain stay short:
+//   E  : Sigma_{i,J}  = -sum_{k far} Sigma_{i,k} Lhat_{k,J}     i far
+//   E1 : Sigma_{J+1,J} = -sum_{k far} Sigma_{J+1,k} Lhat_{k,J}
+//   L  : Sigma_{i,J} -= Sigma_{i,J+1} Lhat_{J+1,J}               i far
+//   L1 : Sigma_{J+1,J} -= Sigma_{J+1,J+1} Lhat_{J+1,J}
+//   DA : Sigma_JJ = X_J^T X_J - sum_{i far} Lhat_{i,J}^T Sigma_{i,J}       (lower blocks)
+//   DB : Sigma_JJ -= Lhat_{J+1,J}^T Sigma_{J+1,J}, then mirrored           (lower blocks)
+// Dependencies (counters per tile column, "done(J)" = its last group):
+//   E(J): done(J+2);  E1(J), L(J): off-diagonals of J+1 final (and E(J));
+//   L1(J): Sigma_{J+1,J+1} final and E1(J);  DA(J): L(J);  DB(J): DA(J), L1(J).
+// Ticket order: groups J = N-1 .. 0, group J = [E(J-1), E1(J), L(J), L1(J),
+// DA(J), DB(J)] (group N-1 also starts with E(N-1)); every task depends only
+// on tasks of earlier groups or earlier in its own group.
+enum { P2_E = 0, P2_E1, P2_L, P2_L1, P2_DA, P2_DB, P2_KINDS };
+
+struct P2 {
+    double* S;
+    const double* W;
+    Lay L;
+    int* group_off;  // [N+1]: first ticket of group J = N-1-q at group_off[q]
+    int* cnt;        // [P2_KINDS * N] finished tasks per kind and tile column
+    int ntasks;
+};
+
+struct P2Counts {
+    int n[P2_KINDS];
+};
+
+// Task counts of tile column J.
+__host__ __device__ inline P2Counts p2_counts(const Lay& L, int64_t J) {
+    P2Counts c;
+    const int s = L.s(J);
+    const int C32 = L.b / 32;
+    const int far = s > 1 ? s - 1 : 0;
+    const int nf32 = far * C32 + (L.ap + 31) / 32;
+    c.n[P2_E] = nf32 * C32;
+    c.n[P2_E1] = s >= 1 ? C32 * C32 : 0;
+    c.n[P2_L] = s >= 1 ? nf32 * C32 : 0;
+    c.n[P2_L1] = s >= 1 ? C32 * C32 : 0;
+    c.n[P2_DA] = C32 * (C32 + 1) / 2;
+    c.n[P2_DB] = s >= 1 ? C32 * (C32 + 1) / 2 : 0;
+    return c;
 }
 
-// Phase 2, off-diagonal tiles of column J ("GEMM" of Alg. 3):
-//   Sigma_{i,J} = - sum_{k in S(J)} Sigma_{i,k} Lhat_{k,J},  i in S(J)
-// S(J) = band tiles J+1..J+s and the arrow.  Sigma_{i,k} with i < k is read
-// as the transpose of the stored lower tile.
-__global__ __launch_bounds__(NT) void k_sigma_off(double* S, const double* W, Lay L, int64_t J) {
-    __shared__ double smem[GB_SMEM_DOUBLES];
-    const int nb64 = L.b / 64;
-    const int s = L.s(J);
-    const int blk = blockIdx.x / nb64, cb = blockIdx.x % nb64;
-    int d, rb;
-    if (blk < s * nb64) { d = 1 + blk / nb64; rb = blk % nb64; }
-    else { d = ARW; rb = blk - s * nb64; }
-    const int vo = (d == ARW) ? imin_(64, L.ap - rb * 64) : 64;
-    GAcc g;
-    gacc_zero(g);
-    for (int e = 1; e <= s; ++e) {
-        gemm_acc(g, sigma_block(L, S, J, d, rb, e),
-                 opnd(W + L.band(J, e) + (int64_t)cb * 64 * L.b, L.b, 0, 64), L.b, smem);
+// Tasks in group J (see the ticket order above).
+__host__ __device__ inline int p2_group_tasks(const Lay& L, int64_t J) {
+    const P2Counts c = p2_counts(L, J);
+    int t = c.n[P2_E1] + c.n[P2_L] + c.n[P2_L1] + c.n[P2_DA] + c.n[P2_DB];
+    if (J >= 1) t += p2_counts(L, J - 1).n[P2_E];
+    if (J == L.nt - 1) t += c.n[P2_E];
+    return t;
+}
+
+__global__ void k_p2_setup(P2 p, int* ticket, int* err) {
+    const Lay& L = p.L;
+    for (int64_t i = threadIdx.x; i < P2_KINDS * L.nt; i += blockDim.x) p.cnt[i] = 0;
+    if (threadIdx.x == 0) {
+        int acc = 0;
+        for (int64_t q = 0; q < L.nt; ++q) {
+            p.group_off[q] = acc;
+            acc += p2_group_tasks(L, L.nt - 1 - q);
+        }
+        p.group_off[L.nt] = acc;
+        *ticket = 0;
+        *err = 0;
     }
-    if (L.ap > 0)
-        gemm_acc(g, sigma_block(L, S, J, d, rb, ARW),
-                 opnd(W + L.arrow(J) + (int64_t)cb * 64 * L.ap, L.ap, 0, 64), L.ap, smem);
+}
+
+// Operand A = Sigma restricted to a block of rows and a tile of k:
+// rows = block rbl (of rb rows) of tile J+d (d >= 1) or of the arrow (ARW);
+// k = tile J+e (e >= 1) or the arrow.
+__device__ inline void p2_sigma_rows(const Lay& L, const double* S, int64_t J, int d, int rbl, int rb, int e,
+                                     const double*& a, int64_t& lda, int& ta, int& av) {
+    av = rb;
+    if (d != ARW && e != ARW) {
+        if (d > e) { a = S + L.band(J + e, d - e) + rbl * rb; lda = L.b; ta = 0; }
+        else if (d == e) { a = S + L.band(J + d, 0) + rbl * rb; lda = L.b; ta = 0; }
+        else { a = S + L.band(J + d, e - d) + (int64_t)rbl * rb * L.b; lda = L.b; ta = 1; }
+    } else if (d != ARW) {
+        a = S + L.arrow(J + d) + (int64_t)rbl * rb * L.ap; lda = L.ap; ta = 1;
+    } else {
+        av = imin_(rb, L.ap - rbl * rb);
+        lda = L.ap; ta = 0;
+        a = (e != ARW) ? S + L.arrow(J + e) + rbl * rb : S + L.corner() + rbl * rb;
+    }
+}
+
+// Row block rbg (of rb rows) among the far rows of S(J): tiles J+2..J+s, arrow.
+__device__ inline void p2_far_row(const Lay& L, int s, int rbg, int rb, int& d, int& rbl) {
+    const int per = L.b / rb;
+    const int far = s > 1 ? s - 1 : 0;
+    if (rbg < far * per) { d = 2 + rbg / per; rbl = rbg % per; }
+    else { d = ARW; rbl = rbg - far * per; }
+}
+
+// Is "done(J)" reached (all of column J final)?  Waits on the counters.
+__device__ inline bool p2_wait_done(const P2& p, const Sched& sc, int64_t J, int* sh) {
+    const P2Counts c = p2_counts(p.L, J);
+    const int64_t N = p.L.nt;
+    if (c.n[P2_DB] > 0) return sched_wait(sc, &p.cnt[P2_DB * N + J], c.n[P2_DB], sh);
+    return sched_wait(sc, &p.cnt[P2_DA * N + J], c.n[P2_DA], sh);
+}
+
+// Are the off-diagonal tiles of column J final?
+__device__ inline bool p2_wait_offdiag(const P2& p, const Sched& sc, int64_t J, int* sh) {
+    const P2Counts c = p2_counts(p.L, J);
+    const int64_t N = p.L.nt;
+    if (c.n[P2_L1] > 0)
+        return sched_wait(sc, &p.cnt[P2_L * N + J], c.n[P2_L], sh) &&
+               sched_wait(sc, &p.cnt[P2_L1 * N + J], c.n[P2_L1], sh);
+    return sched_wait(sc, &p.cnt[P2_E * N + J], c.n[P2_E], sh);
+}
+
+#define P2_SMEM_DOUBLES (WS_SMEM_DOUBLES + 32 * WR_LD)
+#define P2_WG_PER_CU 2
+
+// One Phase 2 task: a 32 x 32 output block, its reduction spread over the 4
+// wavefronts.
+__device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, int u, bool mirror_da, double* smem,
+                                           double* red, int t) {
+    const Lay& L = p.L;
+    const int C32 = L.b / 32;
+    const int s = L.s(J);
+    const int far = s > 1 ? s - 1 : 0;
+    // output block and the reduction: L, L1, DB run over tile J+1 only (one
+    // segment of b); DA over the far tiles and the arrow
+    int d = 0, rbl = 0, rb = 0, cb = 0, nseg, ktot;
+    const bool rowtask = kind <= P2_L1;            // E, E1, L, L1
+    const bool kfar = kind == P2_E || kind == P2_E1;  // reduction over the far tiles
+    if (rowtask) {
+        if (kind == P2_E || kind == P2_L) p2_far_row(L, s, u / C32, 32, d, rbl);
+        else { d = 1; rbl = u / C32; }
+        cb = u % C32;
+        nseg = kfar ? far + (L.ap > 0 ? 1 : 0) : 1;
+        ktot = kfar ? far * L.b + L.ap : L.b;
+    } else {
+        tri_decode(u, rb, cb);
+        nseg = (kind == P2_DA) ? far + (L.ap > 0 ? 1 : 0) : 1;
+        ktot = (kind == P2_DA) ? far * L.b + L.ap : L.b;
+    }
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    wave_segs(acc, nseg, ktot, smem, [&](int q) {
+        if (rowtask) {
+            const int e = kfar ? ((q < far) ? q + 2 : ARW) : 1;
+            const double* a; int64_t lda; int ta, av;
+            p2_sigma_rows(L, p.S, J, d, rbl, 32, e, a, lda, ta, av);
+            if (e != ARW)
+                return mkseg(a, lda, ta, p.W + L.band(J, e) + (int64_t)cb * 32 * L.b, L.b, 0, L.b, av, 1, 0);
+            return mkseg(a, lda, ta, p.W + L.arrow(J) + (int64_t)cb * 32 * L.ap, L.ap, 0, L.ap, av, 1, 0);
+        }
+        const int e = (kind == P2_DB) ? 1 : ((q < far) ? q + 2 : ARW);
+        if (e != ARW)
+            return mkseg(p.W + L.band(J, e) + (int64_t)rb * 32 * L.b, L.b, 1,
+                         p.S + L.band(J, e) + (int64_t)cb * 32 * L.b, L.b, 0, L.b, 32, 0, 1);
+        return mkseg(p.W + L.arrow(J) + (int64_t)rb * 32 * L.ap, L.ap, 1,
+                     p.S + L.arrow(J) + (int64_t)cb * 32 * L.ap, L.ap, 0, L.ap, 32, 0, 1);
+    });
     double* O;
     int64_t ldo;
-    if (d != ARW) { O = S + L.band(J, d) + rb * 64 + (int64_t)cb * 64 * L.b; ldo = L.b; }
-    else { O = S + L.arrow(J) + rb * 64 + (int64_t)cb * 64 * L.ap; ldo = L.ap; }
-    gemm_store(g, smem, -1.0, 0.0, nullptr, 0, O, ldo, vo, 64);
-}
-
-// Phase 2, diagonal tile of column J ("LAUUM" then "GEMM" of Alg. 3):
-//   Sigma_JJ = X_J^T X_J - sum_{k in S(J)} Lhat_{k,J}^T Sigma_{k,J}
-// Lower 64 x 64 blocks, mirrored.
-__global__ __launch_bounds__(NT) void k_sigma_diag(double* S, const double* W, Lay L, int64_t J) {
-    __shared__ double smem[GB_SMEM_DOUBLES];
-    const int s = L.s(J);
-    int rb, cb;
-    tri_decode(blockIdx.x, rb, cb);
-    GAcc g;
-    gacc_zero(g);
-    for (int e = 1; e <= s; ++e) {
-        gemm_acc(g, opnd(W + L.band(J, e) + (int64_t)rb * 64 * L.b, L.b, 1, 64),
-                 opnd(S + L.band(J, e) + (int64_t)cb * 64 * L.b, L.b, 0, 64), L.b, smem);
+    int mv = 32;
+    if (rowtask) {
+        if (d != ARW) { O = p.S + L.band(J, d) + rbl * 32 + (int64_t)cb * 32 * L.b; ldo = L.b; }
+        else { O = p.S + L.arrow(J) + rbl * 32 + (int64_t)cb * 32 * L.ap; ldo = L.ap; mv = imin_(32, L.ap - rbl * 32); }
+    } else {
+        O = p.S + L.band(J, 0) + rb * 32 + (int64_t)cb * 32 * L.b;
+        ldo = L.b;
     }
-    if (L.ap > 0)
-        gemm_acc(g, opnd(W + L.arrow(J) + (int64_t)rb * 64 * L.ap, L.ap, 1, 64),
-                 opnd(S + L.arrow(J) + (int64_t)cb * 64 * L.ap, L.ap, 0, 64), L.ap, smem);
-    double* T = S + L.band(J, 0);
-    gemm_store_sym(g, smem, -1.0, 1.0, T + rb * 64 + (int64_t)cb * 64 * L.b, L.b,
-                   T + rb * 64 + (int64_t)cb * 64 * L.b, T + cb * 64 + (int64_t)rb * 64 * L.b, L.b,
-                   rb == cb, 64, 64);
+    TRACE(t, 4, wall_clock64());
+    wave_reduce(acc, smem, red);
+    TRACE(t, 5, wall_clock64());
+    // out = base - red, base = the partial already stored (L, L1, DB),
+    // Sigma_JJ's initial value X^T X (DA), or 0 (E, E1)
+    const bool mirror = (kind == P2_DB) || (kind == P2_DA && mirror_da);
+    const bool diag = (kind >= P2_DA) && rb == cb;
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int i = e & 31, j = e >> 5;
+        if (i >= mv || (diag && i < j)) continue;
+        const double base = kfar ? 0.0 : ld_coh(O + i + (int64_t)j * ldo);
+        red[j * WR_LD + i] = base - red[j * WR_LD + i];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int i = e & 31, j = e >> 5;
+        if (i >= mv) continue;
+        if (diag && i < j) {
+            if (mirror) st_coh(O + i + (int64_t)j * ldo, red[i * WR_LD + j]);
+            continue;
+        }
+        const double v = red[j * WR_LD + i];
+        st_coh(O + i + (int64_t)j * ldo, v);
+        if (mirror && !diag) st_coh(p.S + L.band(J, 0) + (cb * 32 + j) + (int64_t)(rb * 32 + i) * L.b, v);
+    }
+    TRACE(t, 6, wall_clock64());
 }
 
-__global__ void k_selinv_final(const int* info_ws, int* info) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *info = *info_ws;
+__global__ __launch_bounds__(NT) void k_phase2(P2 p, Sched sc) {
+    __shared__ double smem[P2_SMEM_DOUBLES];
+    __shared__ int sh[2];
+    double* red = smem + WS_SMEM_DOUBLES;
+    const Lay& L = p.L;
+    const int64_t N = L.nt;
+    for (;;) {
+        const int t = sched_next(sc, p.ntasks, &sh[0]);
+        if (t < 0) break;
+        TRACE(t, 0, wall_clock64());
+        int lo = 0, hi = (int)N;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (p.group_off[mid] <= t) lo = mid; else hi = mid;
+        }
+        const int64_t G = N - 1 - lo;       // group
+        int u = t - p.group_off[lo];
+        // decode (kind, J, index) inside group G
+        int kind = -1;
+        int64_t J = G;
+        {
+            const P2Counts cg = p2_counts(L, G);
+            if (G == N - 1) {
+                if (u < cg.n[P2_E]) kind = P2_E;
+                else u -= cg.n[P2_E];
+            }
+            if (kind < 0 && G >= 1) {
+                const int ne = p2_counts(L, G - 1).n[P2_E];
+                if (u < ne) { kind = P2_E; J = G - 1; }
+                else u -= ne;
+            }
+            for (int k = P2_E1; kind < 0 && k < P2_KINDS; ++k) {
+                if (u < cg.n[k]) kind = k;
+                else u -= cg.n[k];
+            }
+        }
+        const P2Counts c = p2_counts(L, J);
+        int* my = &p.cnt[kind * N + J];
+
+        // dependencies
+        bool ok = true;
+        switch (kind) {
+            case P2_E: if (J + 2 < N) ok = p2_wait_done(p, sc, J + 2, &sh[1]); break;
+            case P2_E1: ok = p2_wait_offdiag(p, sc, J + 1, &sh[1]); break;
+            case P2_L:
+                ok = p2_wait_offdiag(p, sc, J + 1, &sh[1]) && sched_wait(sc, &p.cnt[P2_E * N + J], c.n[P2_E], &sh[1]);
+                break;
+            case P2_L1:
+                ok = p2_wait_done(p, sc, J + 1, &sh[1]) && sched_wait(sc, &p.cnt[P2_E1 * N + J], c.n[P2_E1], &sh[1]);
+                break;
+            case P2_DA:
+                ok = (c.n[P2_L] > 0) ? sched_wait(sc, &p.cnt[P2_L * N + J], c.n[P2_L], &sh[1])
+                                     : sched_wait(sc, &p.cnt[P2_E * N + J], c.n[P2_E], &sh[1]);
+                break;
+            default:
+                ok = sched_wait(sc, &p.cnt[P2_DA * N + J], c.n[P2_DA], &sh[1]) &&
+                     sched_wait(sc, &p.cnt[P2_L1 * N + J], c.n[P2_L1], &sh[1]);
+        }
+        if (!ok) break;
+        TRACE(t, 1, wall_clock64());
+
+        p2_task_small(p, kind, J, u, c.n[P2_DB] == 0, smem, red, t);
+        sched_signal(sc, my, t);
+        TRACE(t, 2, wall_clock64());
+        TRACE(t, 3, (unsigned long long)kind | ((unsigned long long)J << 8) | ((unsigned long long)blockIdx.x << 40));
+        TRACE(t, 7, (unsigned long long)__smid());
+    }
+}
+
+__global__ void k_selinv_final(const int* info_ws, const int* err, int* info) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *info = (*err != 0) ? *err : *info_ws;
 }
 
 // ---------------------------------------------------------------------------
@@ -499,6 +714,46 @@ static void tm_drop() {
         tm_end(_tm, kind, st);                                                 \
     } while (0)
 
+// Per-device facts used to size persistent launches (queried once).
+struct DevInfo {
+    int cus = 0;
+    int64_t clock_khz = 0;
+};
+static std::mutex g_dmu;
+static DevInfo g_dev[64];
+
+static int dev_info(DevInfo* out) {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return STILES_EHIP;
+    std::lock_guard<std::mutex> g(g_dmu);
+    if (g_dev[d].cus == 0) {
+        int cus = 0, khz = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess) return STILES_EHIP;
+        if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, d) != hipSuccess) return STILES_EHIP;
+        g_dev[d].cus = cus > 0 ? cus : 1;
+        g_dev[d].clock_khz = khz > 0 ? khz : 100000;
+    }
+    *out = g_dev[d];
+    return 0;
+}
+
+// Wait limit of the device-side spin loops: STILES_SPIN_LIMIT_MS (default
+// 4000 ms).  STILES_DEBUG_WITHHOLD=<ticket> makes that task skip its ready
+// signal, to exercise the timeout path.
+static int64_t spin_limit_ticks(const DevInfo& di) {
+    double ms = 4000.0;
+    if (const char* e = getenv("STILES_SPIN_LIMIT_MS")) {
+        const double v = atof(e);
+        if (v > 0) ms = v;
+    }
+    return (int64_t)(ms * (double)di.clock_khz);
+}
+
+static int debug_withhold() {
+    if (const char* e = getenv("STILES_DEBUG_WITHHOLD")) return atoi(e);
+    return -1;
+}
+
 static int grid_for(int64_t work) {
     int64_t g = (work + NT - 1) / NT;
     if (g > 65536) g = 65536;
@@ -507,6 +762,14 @@ static int grid_for(int64_t work) {
 }
 
 extern "C" {
+
+#ifdef STILES_TASK_TRACE
+int stiles_debug_trace_read(unsigned long long* host, size_t n_tasks) {
+    if (n_tasks > STILES_TRACE_MAX) n_tasks = STILES_TRACE_MAX;
+    return hipMemcpyFromSymbol(host, HIP_SYMBOL(g_trace), STILES_TRACE_SLOTS * n_tasks * sizeof(unsigned long long), 0,
+                               hipMemcpyDeviceToHost) == hipSuccess ? 0 : STILES_EHIP;
+}
+#endif
 
 int stiles_version(void) { return 100; }
 
@@ -576,9 +839,14 @@ size_t stiles_factor_workspace_bytes(const stiles_layout* lay) {
            sizeof(double) * (size_t)((int64_t)lay->tile * lay->tile + 256 * 256);
 }
 
+// selinv workspace: head (info, ticket, error words), the Phase 1 tiles
+// (inverted diagonal tiles, Lhat, corner inverse) in the tile layout, then
+// the Phase 2 step offsets and ready counters.
+static size_t selinv_flags_ints(const stiles_layout* lay) { return (size_t)(7 * lay->nt + 1); }
+
 size_t stiles_selinv_workspace_bytes(const stiles_layout* lay) {
     if (!lay) return 0;
-    return WS_HEAD + sizeof(double) * (size_t)lay->total_doubles;
+    return WS_HEAD + sizeof(double) * (size_t)lay->total_doubles + sizeof(int) * selinv_flags_ints(lay);
 }
 
 int stiles_pack(const double* ab, const double* arrow_rows, const double* corner, double* tiles,
@@ -697,15 +965,32 @@ int stiles_selinv(const double* Lm, double* S, int64_t n, int64_t bandwidth, int
         const int64_t g = (L.nt + (L.ap > 0)) * (int64_t)per;
         LAUNCH(STILES_TK_PHASE1, k_lauum_all, dim3((unsigned)g), dim3(NT), 0, st, (const double*)W, S, L);
     }
-    // Phase 2, bottom-right to top-left
-    for (int64_t J = L.nt - 1; J >= 0; --J) {
-        const int s = L.s(J);
-        const int rows = s * nb64 + nab;
-        if (rows == 0) continue;
-        LAUNCH(STILES_TK_SIGMA_OFF, k_sigma_off, dim3(rows * nb64), dim3(NT), 0, st, S, (const double*)W, L, J);
-        LAUNCH(STILES_TK_SIGMA_DIAG, k_sigma_diag, dim3(nb64 * (nb64 + 1) / 2), dim3(NT), 0, st, S, (const double*)W, L, J);
+    // Phase 2, bottom-right to top-left, one persistent launch
+    {
+        DevInfo di;
+        if (dev_info(&di)) return STILES_EHIP;
+        P2 p;
+        p.S = S;
+        p.W = W;
+        p.L = L;
+        int* fl = (int*)(W + L.total);
+        p.group_off = fl;
+        p.cnt = fl + L.nt + 1;
+        int64_t ntasks = 0;
+        for (int64_t J = 0; J < L.nt; ++J) ntasks += p2_group_tasks(L, J);
+        if (ntasks > 0x7fffffff) return -3;
+        p.ntasks = (int)ntasks;
+        Sched sc;
+        sc.ticket = winfo + 16;
+        sc.err = winfo + 32;
+        sc.spin_limit = spin_limit_ticks(di);
+        sc.withhold = debug_withhold();
+        LAUNCH(STILES_TK_OTHER, k_p2_setup, dim3(1), dim3(NT), 0, st, p, sc.ticket, sc.err);
+        const int grid = (int)std::min<int64_t>(ntasks, P2_WG_PER_CU * (int64_t)di.cus);
+        LAUNCH(STILES_TK_PHASE2, k_phase2, dim3(grid), dim3(NT), 0, st, p, sc);
     }
-    LAUNCH(STILES_TK_OTHER, k_selinv_final, dim3(1), dim3(64), 0, st, (const int*)winfo, (int*)info);
+    LAUNCH(STILES_TK_OTHER, k_selinv_final, dim3(1), dim3(64), 0, st, (const int*)winfo, (const int*)(winfo + 32),
+           (int*)info);
     return 0;
 }
 

@@ -37,7 +37,7 @@ EXPORTED = (
     "stiles_timing_collect",
 )
 
-TIMING_KINDS = ("potrf", "trsm", "update", "phase1", "sigma_off", "sigma_diag", "other")
+TIMING_KINDS = ("potrf", "trsm", "update", "phase1", "phase2", "factor", "other")
 
 
 class _CLayout(ctypes.Structure):

@@ -143,3 +143,28 @@ def test_bitwise_repeatable_and_in_place(torch_cuda):
     assert torch.equal(L1, L2) and torch.equal(S1, S2)
     assert torch.equal(L1, L3)
     assert float(ld1.item()) == float(ld2.item()) == float(ld3.item())
+
+
+def test_watchdog_turns_a_missing_signal_into_an_error(torch_cuda, monkeypatch):
+    """Phase 2 task 0 never signals (host-side test hook); the consumers'
+    bounded waits expire and every workgroup leaves with STILES_ETIMEOUT."""
+    import torch
+    from gpu_util import to_device
+    from paper_2504_19171_amd import stiles as st
+    M = inputs.arrowhead_spd(700, 60, 10, seed=4)
+    lay = st.layout(M.n, 60, 10, 64)
+    A = st.pack(*to_device(M, "cuda:0"), lay)
+    L, _, info = st.factor(A, lay)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    monkeypatch.setenv("STILES_DEBUG_WITHHOLD", "0")
+    monkeypatch.setenv("STILES_SPIN_LIMIT_MS", "20")
+    print("watchdog: withholding ticket 0", flush=True)
+    S, sinfo = st.selinv(L, lay)
+    torch.cuda.synchronize()
+    assert int(sinfo.item()) == st.STILES_ETIMEOUT
+    monkeypatch.delenv("STILES_DEBUG_WITHHOLD")
+    monkeypatch.delenv("STILES_SPIN_LIMIT_MS")
+    S, sinfo = st.selinv(L, lay)      # and the next call is clean again
+    torch.cuda.synchronize()
+    assert int(sinfo.item()) == 0
