@@ -34,11 +34,14 @@
  *   Sigma on real indices and log det are unchanged (log 1 = 0).
  * - Pointers named "device" are HIP device pointers; the caller allocates and
  *   frees every buffer.  The library never retains or frees caller memory and
- *   allocates nothing.
+ *   allocates no device memory.
  * - `stream` is a hipStream_t (NULL = the default stream).  Every call only
  *   enqueues work on `stream` and returns; results are ready when the stream
  *   is.  Calls on different streams may overlap if they use different buffers
- *   and workspaces.
+ *   and workspaces.  stiles_factor forks part of its work onto one internal
+ *   stream per device (default priority, created with a few events on first
+ *   use and kept until the process ends) and joins it back into `stream`
+ *   before its last kernel, so `stream` still orders everything.
  * - Return value: 0 when the work was enqueued; -i when argument i (1-based)
  *   is invalid; STILES_EHIP when a HIP call failed.  Numerical outcomes are
  *   reported in the device `info` word (see stiles_factor / stiles_selinv).

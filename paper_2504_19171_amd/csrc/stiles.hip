@@ -19,6 +19,7 @@
 #include "tile_ops.hpp"
 #include "persist.hpp"
 #include "wave_gemm.hpp"
+#include "potrf3.hpp"
 
 #define NT 256
 
@@ -139,25 +140,6 @@ __global__ __launch_bounds__(NT) void k_potrf(double* M, int64_t ld, int m, doub
     }
 }
 
-// Rows of the panel below tile J (band tiles J+1..J+s, then the arrow tile),
-// one 64-row block per workgroup: C <- C * X^T with X = L_JJ^{-1} (TRSM).
-__device__ inline void panel_rows(const Lay& L, double* base, int64_t J, int blk, double*& C,
-                                  int64_t& ld, int& valid) {
-    const int nb64 = L.b / 64;
-    const int s = L.s(J);
-    if (blk < s * nb64) {
-        const int d = 1 + blk / nb64, rb = blk % nb64;
-        C = base + L.band(J, d) + rb * 64;
-        ld = L.b;
-        valid = 64;
-    } else {
-        const int rb = blk - s * nb64;
-        C = base + L.arrow(J) + rb * 64;
-        ld = L.ap;
-        valid = imin_(64, L.ap - rb * 64);
-    }
-}
-
 // In place: columns are produced last block first, so every column block
 // read later is still unmodified (X^T is upper triangular).
 __device__ inline void trsm_rows(double* C, int64_t ld, int valid, const double* X, int64_t ldx,
@@ -170,15 +152,6 @@ __device__ inline void trsm_rows(double* C, int64_t ld, int valid, const double*
     }
 }
 
-__global__ __launch_bounds__(NT) void k_trsm_panel(double* Lm, Lay L, int64_t J, const double* X) {
-    __shared__ double smem[GB_SMEM_DOUBLES];
-    double* C;
-    int64_t ld;
-    int valid;
-    panel_rows(L, Lm, J, blockIdx.x, C, ld, valid);
-    trsm_rows(C, ld, valid, X, L.b, L.b, smem);
-}
-
 // Generic TRSM on a contiguous row panel (used for the blocked corner).
 __global__ __launch_bounds__(NT) void k_trsm_generic(double* C, int64_t ld, int rows, const double* X,
                                                     int64_t ldx, int ncols) {
@@ -187,71 +160,179 @@ __global__ __launch_bounds__(NT) void k_trsm_generic(double* C, int64_t ld, int 
     trsm_rows(C + rb * 64, ld, imin_(64, rows - rb * 64), X, ldx, ncols, smem);
 }
 
-// Trailing update after tile column J (right-looking):
-//   band tiles (J+d, J+e), 1 <= e <= d <= s:  -= L_{J+d,J} L_{J+e,J}^T
-//   arrow tiles (A, J+e):                      -= L_{A,J}   L_{J+e,J}^T
-//   corner:                                    -= L_{A,J}   L_{A,J}^T
-// One 64 x 64 output block per workgroup; diagonal tiles and the corner only
-// get their lower blocks.
-__global__ __launch_bounds__(NT) void k_update(double* Lm, Lay L, int64_t J) {
-    __shared__ double smem[GB_SMEM_DOUBLES];
-    const int nb64 = L.b / 64;
-    const int s = L.s(J);
-    const int nab = arrow_blocks(L.ap);
-    int t = blockIdx.x;
-    const double *Ap, *Bp;
-    int64_t lda, ldb, ldo;
-    int va = 64, vb = 64;
-    double* O;
-    // band pairs
-    for (int d = 1; d <= s; ++d) {
-        for (int e = 1; e <= d; ++e) {
-            const int cnt = (d == e) ? nb64 * (nb64 + 1) / 2 : nb64 * nb64;
+// ---------------------------------------------------------------------------
+// Factor kernels of the band tile columns
+// ---------------------------------------------------------------------------
+
+// POTRF of one diagonal tile (m = b) plus the inverses of its 64 x 64
+// diagonal blocks (for the panel TRSM): X64 + q*4096, 64 x 64 column-major.
+__global__ __launch_bounds__(NT) void k_potrf_x64(double* M, int64_t ld, int m, double* X64, double* ldp, int* info,
+                                                 int64_t col_base) {
+    extern __shared__ double smem[];
+    int fail;
+    double s, c;
+    potrf_tile(M, ld, m, smem, &fail, &s, &c);
+    if (threadIdx.x == 0) {
+        ldp[0] = s;
+        ldp[1] = c;
+        if (fail >= 0) atomicMin(info, (int)(col_base + fail + 1));
+    }
+    __syncthreads();
+    inv64_blocks(M, ld, X64, m, smem);
+}
+
+// POTRF of one diagonal tile with the register-resident left-looking kernel
+// (potrf3.hpp), plus the 64 x 64 diagonal-block inverses of L.
+__global__ __launch_bounds__(NT) void k_potrf3(double* M, int64_t ld, int m, double* X64, double* ldp, int* info,
+                                              int64_t col_base) {
+    __shared__ P3Smem sm;
+    int fail;
+    double s, c;
+    potrf3(M, ld, m, X64, sm, &fail, &s, &c);
+    if (threadIdx.x == 0) {
+        ldp[0] = s;
+        ldp[1] = c;
+        if (fail >= 0) atomicMin(info, (int)(col_base + fail + 1));
+    }
+}
+
+// Panel TRSM, one 16-row block per workgroup: R = C L_JJ^{-T} in place, by
+// forward substitution over the 64-column blocks q of the tile,
+//   Z_q = C_q - sum_{q' < q} R_q' L_{q,q'}^T,   R_q = Z_q X64_q^T,
+// with the transposed products formed on the matrix cores (Z^T = C^T - L R^T,
+// R^T = X64 Z^T) so that every global access runs down a column.  Row block
+// g0 + blockIdx.x of the rows below tile J: band tiles J+1..J+s (b/16 blocks
+// each), then the arrow tile (a_p/16 blocks).  Wavefront w owns columns
+// 64q + 16w .. 64q + 16w + 15 of each step.
+#define TR_LD 16
+__global__ __launch_bounds__(NT) void k_trsm16(double* Lm, Lay L, int64_t J, const double* X64, int g0) {
+    __shared__ double sR[256 * TR_LD];   // R, [column][row]
+    __shared__ double sZ[64 * TR_LD];    // Z of the current step, [column][row]
+    const int g = g0 + blockIdx.x;
+    const int nbr = L.b / 16, s = L.s(J);
+    double* C;
+    int ld;
+    if (g < s * nbr) { C = Lm + L.band(J, 1 + g / nbr) + (g % nbr) * 16; ld = L.b; }
+    else { C = Lm + L.arrow(J) + (g - s * nbr) * 16; ld = L.ap; }
+    const double* Ljj = Lm + L.band(J, 0);
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int b = L.b;
+    const int nq = b / 64;
+    for (int q = 0; q < nq; ++q) {
+        const int c0 = 64 * q + 16 * w;
+        // Z^T tile (columns c0.., all 16 rows): element r = Z^T[4r + lk][li] = Z[li][c0 + 4r + lk]
+        dbl4 a0, a1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < 4; ++r) a0[r] = C[li + (int64_t)(c0 + 4 * r + lk) * ld];
+        const int K = 64 * q;
+        for (int k = 0; k < K; k += 8) {
+            const double av0 = -Ljj[(c0 + li) + (int64_t)(k + lk) * b];
+            const double bv0 = sR[(k + lk) * TR_LD + li];
+            const double av1 = -Ljj[(c0 + li) + (int64_t)(k + 4 + lk) * b];
+            const double bv1 = sR[(k + 4 + lk) * TR_LD + li];
+            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av0, bv0, a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av1, bv1, a1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sZ[(16 * w + 4 * r + lk) * TR_LD + li] = a0[r] + a1[r];
+        __syncthreads();
+        // R^T rows 16w.. of block q = X64_q(rows 16w..) Z^T; X64 is lower triangular
+        const double* Xq = X64 + (int64_t)q * 4096;
+        dbl4 o0 = {0.0, 0.0, 0.0, 0.0}, o1 = {0.0, 0.0, 0.0, 0.0};
+        const int KX = 16 * (w + 1);
+        for (int k = 0; k < KX; k += 8) {
+            const double av0 = Xq[(16 * w + li) + (k + lk) * 64];
+            const double bv0 = sZ[(k + lk) * TR_LD + li];
+            o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av0, bv0, o0, 0, 0, 0);
+            const double av1 = Xq[(16 * w + li) + (k + 4 + lk) * 64];
+            const double bv1 = sZ[(k + 4 + lk) * TR_LD + li];
+            o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av1, bv1, o1, 0, 0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const double v = o0[r] + o1[r];
+            sR[(c0 + 4 * r + lk) * TR_LD + li] = v;
+            C[li + (int64_t)(c0 + 4 * r + lk) * ld] = v;
+        }
+        __syncthreads();
+    }
+}
+
+// Trailing update after tile column J on 32 x 32 blocks (reduction over the
+// b columns of tile J spread over 4 wavefronts):
+//   band (J+d, J+e), 1 <= e <= d <= s:  -= L_{J+d,J} L_{J+e,J}^T   (lower blocks when d == e)
+//   arrow (A, J+e):                      -= L_{A,J} L_{J+e,J}^T
+//   corner (lower blocks):               -= L_{A,J} L_{A,J}^T
+__host__ __device__ inline int upd32_count(const Lay& L, int64_t J) {
+    const int C32 = L.b / 32, s = L.s(J), na = (L.ap + 31) / 32;
+    int cnt = 0;
+    for (int d = 1; d <= s; ++d)
+        for (int e = 1; e <= d; ++e) cnt += (d == e) ? C32 * (C32 + 1) / 2 : C32 * C32;
+    if (L.ap > 0) cnt += s * na * C32 + na * (na + 1) / 2;
+    return cnt;
+}
+
+__global__ __launch_bounds__(NT) void k_update32(double* Lm, Lay L, int64_t J, int t0) {
+    __shared__ double smem[WS_SMEM_DOUBLES + 32 * WR_LD];
+    double* red = smem + WS_SMEM_DOUBLES;
+    const int C32 = L.b / 32, s = L.s(J), na = (L.ap + 31) / 32;
+    int t = t0 + blockIdx.x;
+    const double *Ap = nullptr, *Bp = nullptr;
+    int64_t lda = L.b, ldb = L.b, ldo = L.b;
+    int va = 32, vb = 32;
+    double* O = nullptr;
+    bool found = false;
+    for (int d = 1; d <= s && !found; ++d) {
+        for (int e = 1; e <= d && !found; ++e) {
+            const int cnt = (d == e) ? C32 * (C32 + 1) / 2 : C32 * C32;
             if (t < cnt) {
                 int rb, cb;
                 if (d == e) tri_decode(t, rb, cb);
-                else { rb = t % nb64; cb = t / nb64; }
-                Ap = Lm + L.band(J, d) + rb * 64; lda = L.b;
-                Bp = Lm + L.band(J, e) + cb * 64; ldb = L.b;
-                O = Lm + L.band(J + e, d - e) + rb * 64 + (int64_t)cb * 64 * L.b; ldo = L.b;
-                goto run;
+                else { rb = t % C32; cb = t / C32; }
+                Ap = Lm + L.band(J, d) + rb * 32;
+                Bp = Lm + L.band(J, e) + cb * 32;
+                O = Lm + L.band(J + e, d - e) + rb * 32 + (int64_t)cb * 32 * L.b;
+                found = true;
+            } else {
+                t -= cnt;
             }
-            t -= cnt;
         }
     }
-    // arrow tiles
-    for (int e = 1; e <= s; ++e) {
-        const int cnt = nab * nb64;
-        if (t < cnt) {
-            const int rb = t % nab, cb = t / nab;
-            Ap = Lm + L.arrow(J) + rb * 64; lda = L.ap; va = imin_(64, L.ap - rb * 64);
-            Bp = Lm + L.band(J, e) + cb * 64; ldb = L.b;
-            O = Lm + L.arrow(J + e) + rb * 64 + (int64_t)cb * 64 * L.ap; ldo = L.ap;
-            goto run;
+    if (!found && L.ap > 0) {
+        for (int e = 1; e <= s && !found; ++e) {
+            const int cnt = na * C32;
+            if (t < cnt) {
+                const int rb = t % na, cb = t / na;
+                Ap = Lm + L.arrow(J) + rb * 32; lda = L.ap; va = imin_(32, L.ap - rb * 32);
+                Bp = Lm + L.band(J, e) + cb * 32;
+                O = Lm + L.arrow(J + e) + rb * 32 + (int64_t)cb * 32 * L.ap; ldo = L.ap;
+                found = true;
+            } else {
+                t -= cnt;
+            }
         }
-        t -= cnt;
+        if (!found) {
+            int rb, cb;
+            tri_decode(t, rb, cb);
+            Ap = Lm + L.arrow(J) + rb * 32; lda = L.ap; va = imin_(32, L.ap - rb * 32);
+            Bp = Lm + L.arrow(J) + cb * 32; ldb = L.ap; vb = imin_(32, L.ap - cb * 32);
+            O = Lm + L.corner() + rb * 32 + (int64_t)cb * 32 * L.ap; ldo = L.ap;
+        }
     }
-    {   // corner (lower blocks)
-        int rb, cb;
-        tri_decode(t, rb, cb);
-        Ap = Lm + L.arrow(J) + rb * 64; lda = L.ap; va = imin_(64, L.ap - rb * 64);
-        Bp = Lm + L.arrow(J) + cb * 64; ldb = L.ap; vb = imin_(64, L.ap - cb * 64);
-        O = Lm + L.corner() + rb * 64 + (int64_t)cb * 64 * L.ap; ldo = L.ap;
+    dbl4 acc[2][2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // B(k, j) = L_cols[j][k]: the transposed access of the column rows
+    const Seg sg = mkseg(Ap, lda, 0, Bp, ldb, 1, L.b, va);
+    wave_segs(acc, 1, L.b, smem, [&](int) { return sg; });
+    wave_reduce(acc, smem, red);
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int i = e & 31, j = e >> 5;
+        if (i < va && j < vb) O[i + (int64_t)j * ldo] -= red[j * WR_LD + i];
     }
-run:
-    GAcc g;
-    gacc_zero(g);
-    gemm_acc(g, opnd(Ap, lda, 0, va), opnd(Bp, ldb, 1, vb), L.b, smem);
-    gemm_store(g, smem, -1.0, 1.0, O, ldo, O, ldo, va, vb);
-}
-
-static int update_blocks(const Lay& L, int64_t J) {
-    const int nb64 = L.b / 64, s = L.s(J), nab = arrow_blocks(L.ap);
-    int cnt = 0;
-    for (int d = 1; d <= s; ++d)
-        for (int e = 1; e <= d; ++e) cnt += (d == e) ? nb64 * (nb64 + 1) / 2 : nb64 * nb64;
-    if (L.ap > 0) cnt += s * nab * nb64 + nab * (nab + 1) / 2;
-    return cnt;
 }
 
 // C (rows x rows, lower blocks) -= P P^T, P rows x K (generic, corner blocking).
@@ -303,6 +384,25 @@ __global__ __launch_bounds__(NT) void k_trtri_all(const double* Lm, double* W, L
         trtri_tile(Lm + L.corner(), L.ap, W + L.corner(), L.ap, L.ap, smem, &bad);
     }
     if (threadIdx.x == 0 && bad) atomicExch(info, STILES_EBADL);
+}
+
+// Rows of the panel below tile J (band tiles J+1..J+s, then the arrow tile),
+// 64-row block blk.
+__device__ inline void panel_rows(const Lay& L, double* base, int64_t J, int blk, double*& C,
+                                  int64_t& ld, int& valid) {
+    const int nb64 = L.b / 64;
+    const int s = L.s(J);
+    if (blk < s * nb64) {
+        const int d = 1 + blk / nb64, rb = blk % nb64;
+        C = base + L.band(J, d) + rb * 64;
+        ld = L.b;
+        valid = 64;
+    } else {
+        const int rb = blk - s * nb64;
+        C = base + L.arrow(J) + rb * 64;
+        ld = L.ap;
+        valid = imin_(64, L.ap - rb * 64);
+    }
 }
 
 // Phase 1, off-diagonal tiles: Lhat_{k,J} = L_{k,J} X_J for the band tiles
@@ -749,6 +849,13 @@ static int64_t spin_limit_ticks(const DevInfo& di) {
     return (int64_t)(ms * (double)di.clock_khz);
 }
 
+// STILES_POTRF=1 selects the 16-panel right-looking diagonal-tile kernel
+// instead of the default left-looking one (for comparisons).
+static int g_potrf_kind = [] {
+    const char* e = getenv("STILES_POTRF");
+    return e ? atoi(e) : 0;
+}();
+
 static int debug_withhold() {
     if (const char* e = getenv("STILES_DEBUG_WITHHOLD")) return atoi(e);
     return -1;
@@ -759,6 +866,33 @@ static int grid_for(int64_t work) {
     if (g > 65536) g = 65536;
     if (g < 1) g = 1;
     return (int)g;
+}
+
+// Second stream (default priority) and events of the factor pipeline, one set
+// per device, created on first use.  The mutex serialises the enqueue of
+// concurrent factor calls on one device (their kernels may still overlap).
+struct Side {
+    hipStream_t s = nullptr;
+    hipEvent_t fork = nullptr, po = nullptr, tr = nullptr, up = nullptr, join = nullptr;
+    std::mutex mu;
+};
+static Side g_side[64];
+
+static int side_get(Side** out) {
+    int d = 0;
+    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return STILES_EHIP;
+    Side& sd = g_side[d];
+    std::lock_guard<std::mutex> g(g_dmu);
+    if (!sd.s) {
+        hipStream_t s;
+        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return STILES_EHIP;
+        hipEvent_t* ev[5] = {&sd.fork, &sd.po, &sd.tr, &sd.up, &sd.join};
+        for (auto e : ev)
+            if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return STILES_EHIP;
+        sd.s = s;
+    }
+    *out = &sd;
+    return 0;
 }
 
 extern "C" {
@@ -833,10 +967,10 @@ int stiles_layout_init(int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile
 
 size_t stiles_factor_workspace_bytes(const stiles_layout* lay) {
     if (!lay) return 0;
-    // head + log det partials (N + 2 blocks) + one b x b inverse + the 256 x 256
-    // inverse of the blocked corner.
+    // head + log det partials (N + 2 blocks) + the 256 x 256 inverse of the
+    // blocked corner + the 64 x 64 diagonal-block inverses of every L_JJ.
     return WS_HEAD + sizeof(double) * (size_t)(2 * (lay->nt + 2)) +
-           sizeof(double) * (size_t)((int64_t)lay->tile * lay->tile + 256 * 256);
+           sizeof(double) * (size_t)(256 * 256 + lay->nt * (int64_t)(lay->tile / 64) * 4096);
 }
 
 // selinv workspace: head (info, ticket, error words), the Phase 1 tiles
@@ -879,8 +1013,13 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     char* ws = (char*)workspace;
     int* winfo = (int*)ws;
     double* ldp = (double*)(ws + WS_HEAD);
-    double* X = ldp + 2 * (L.nt + 2);
-    double* Xc = X + (int64_t)L.b * L.b;
+    double* Xc = ldp + 2 * (L.nt + 2);
+    double* X64 = Xc + 256 * 256;
+    const int64_t x64_per = (int64_t)(L.b / 64) * 4096;
+    Side* sd;
+    if (side_get(&sd)) return STILES_EHIP;
+    std::lock_guard<std::mutex> lk(sd->mu);
+    hipStream_t sb = sd->s;
 
     if (A != Lm) {
         hipEvent_t tm = tm_begin(st);
@@ -888,19 +1027,46 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
         tm_end(tm, STILES_TK_OTHER, st);
     }
     LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, winfo, 0x7fffffff);
-    const size_t potrf_smem_b = sizeof(double) * potrf_smem_doubles(L.b);
+    // Two streams.  The caller's stream carries the dependency chain of the
+    // diagonal tiles: POTRF(J) -> TRSM of tile (J+1, J) -> its SYRK into
+    // (J+1, J+1) -> POTRF(J+1).  The side stream carries the rest of column
+    // J (TRSM of the other rows, the other trailing updates), which overlaps
+    // the next steps of the chain.
+    HIPCHK(hipEventRecord(sd->fork, st));
+    HIPCHK(hipStreamWaitEvent(sb, sd->fork, 0));
+    const size_t po_smem = sizeof(double) * potrf_smem_doubles(L.b);
+    const int nbr = L.b / 16, C32 = L.b / 32;
     for (int64_t J = 0; J < L.nt; ++J) {
-        LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), potrf_smem_b, st, Lm + L.band(J, 0), (int64_t)L.b, L.b, X,
-                           (int64_t)L.b, ldp + 2 * J, winfo, J * (int64_t)L.b);
-        const int rows = L.s(J) * (L.b / 64) + arrow_blocks(L.ap);
-        if (rows > 0) {
-            LAUNCH(STILES_TK_TRSM, k_trsm_panel, dim3(rows), dim3(NT), 0, st, Lm, L, J, (const double*)X);
+        const int s = L.s(J);
+        double* Xj = X64 + J * x64_per;
+        if (g_potrf_kind == 1)
+            LAUNCH(STILES_TK_POTRF, k_potrf_x64, dim3(1), dim3(NT), po_smem, st, Lm + L.band(J, 0), (int64_t)L.b, L.b,
+                   Xj, ldp + 2 * J, winfo, J * (int64_t)L.b);
+        else
+            LAUNCH(STILES_TK_POTRF, k_potrf3, dim3(1), dim3(NT), 0, st, Lm + L.band(J, 0), (int64_t)L.b, L.b, Xj,
+                   ldp + 2 * J, winfo, J * (int64_t)L.b);
+        HIPCHK(hipEventRecord(sd->po, st));
+        const int tr_crit = s >= 1 ? nbr : 0;
+        const int tr_all = s * nbr + L.ap / 16;
+        const int up_crit = s >= 1 ? C32 * (C32 + 1) / 2 : 0;
+        const int up_all = upd32_count(L, J);
+        if (tr_crit > 0) {
+            if (J > 0) HIPCHK(hipStreamWaitEvent(st, sd->up, 0));   // updates of column J-1 into tile (J+1, J)
+            LAUNCH(STILES_TK_TRSM, k_trsm16, dim3(tr_crit), dim3(NT), 0, st, Lm, L, J, (const double*)Xj, 0);
+            HIPCHK(hipEventRecord(sd->tr, st));
+            LAUNCH(STILES_TK_UPDATE, k_update32, dim3(up_crit), dim3(NT), 0, st, Lm, L, J, 0);
         }
-        const int ub = update_blocks(L, J);
-        if (ub > 0) {
-            LAUNCH(STILES_TK_UPDATE, k_update, dim3(ub), dim3(NT), 0, st, Lm, L, J);
-        }
+        HIPCHK(hipStreamWaitEvent(sb, sd->po, 0));
+        if (tr_all > tr_crit)
+            LAUNCH(STILES_TK_TRSM, k_trsm16, dim3(tr_all - tr_crit), dim3(NT), 0, sb, Lm, L, J, (const double*)Xj,
+                   tr_crit);
+        if (tr_crit > 0) HIPCHK(hipStreamWaitEvent(sb, sd->tr, 0));
+        if (up_all > up_crit)
+            LAUNCH(STILES_TK_UPDATE, k_update32, dim3(up_all - up_crit), dim3(NT), 0, sb, Lm, L, J, up_crit);
+        HIPCHK(hipEventRecord(sd->up, sb));
     }
+    HIPCHK(hipEventRecord(sd->join, sb));
+    HIPCHK(hipStreamWaitEvent(st, sd->join, 0));
     int nparts = (int)L.nt;
     if (L.ap > 0) {
         double* Cc = Lm + L.corner();

@@ -91,35 +91,63 @@ __device__ inline void ws_stash(double* s, int contig_x, const double r[8]) {
     }
 }
 
-// acc += A(:, k0:k1) * B(k0:k1, :) for this wavefront; k0, k1 multiples of 16.
-// sw: this wavefront's LDS area (WS_WAVE_DOUBLES doubles).
-__device__ inline void wave_seg(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1, double* sw) {
-    if (k1 <= k0) return;
+#define WS_PD 3   // 16-deep chunks in flight per wavefront (registers)
+
+__device__ inline void ws_mma16(dbl4 (&acc)[2][2], const double* sA, const double* sB) {
     const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+#pragma unroll
+    for (int kk = 0; kk < 16; kk += 4) {
+        const double* pa = sA + (kk + lk) * WS_LD + li;
+        const double* pb = sB + (kk + lk) * WS_LD + li;
+        const double a0 = pa[0], a1 = pa[16], b0 = pb[0], b1 = pb[16];
+        acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
+        acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
+        acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
+        acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    }
+}
+
+// acc += A(:, k0:k1) * B(k0:k1, :) for this wavefront; k0, k1 multiples of 16.
+// sw: this wavefront's LDS area (WS_WAVE_DOUBLES doubles).  Up to WS_PD
+// chunks are being fetched while one is multiplied.
+__device__ inline void wave_seg(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1, double* sw) {
+    const int nch = (k1 - k0) >> 4;
+    if (nch <= 0) return;
     const int ca = !sg.ta, cb = sg.tb;   // A normal / B transposed: contiguous along x
     double* sA = sw;
     double* sB = sw + 16 * WS_LD;
-    double ra[8], rb[8];
-    ws_fetch(sg.a, sg.lda, ca, sg.avalid, k0, sg.ca, ra);
-    ws_fetch(sg.b, sg.ldb, cb, 32, k0, sg.cb, rb);
-    for (int k = k0; k < k1; k += 16) {
-        wave_lds_sync();
-        ws_stash(sA, ca, ra);
-        ws_stash(sB, cb, rb);
-        wave_lds_sync();
-        if (k + 16 < k1) {
-            ws_fetch(sg.a, sg.lda, ca, sg.avalid, k + 16, sg.ca, ra);
-            ws_fetch(sg.b, sg.ldb, cb, 32, k + 16, sg.cb, rb);
-        }
+    double ra[WS_PD][8], rb[WS_PD][8];
 #pragma unroll
-        for (int kk = 0; kk < 16; kk += 4) {
-            const double* pa = sA + (kk + lk) * WS_LD + li;
-            const double* pb = sB + (kk + lk) * WS_LD + li;
-            const double a0 = pa[0], a1 = pa[16], b0 = pb[0], b1 = pb[16];
-            acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
-            acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
-            acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
-            acc[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc[1][1], 0, 0, 0);
+    for (int p = 0; p < WS_PD; ++p) {
+        if (p < nch) {
+            ws_fetch(sg.a, sg.lda, ca, sg.avalid, k0 + 16 * p, sg.ca, ra[p]);
+            ws_fetch(sg.b, sg.ldb, cb, 32, k0 + 16 * p, sg.cb, rb[p]);
+        }
+    }
+    int it = 0;
+    for (; it + WS_PD <= nch; it += WS_PD) {
+#pragma unroll
+        for (int p = 0; p < WS_PD; ++p) {
+            wave_lds_sync();
+            ws_stash(sA, ca, ra[p]);
+            ws_stash(sB, cb, rb[p]);
+            wave_lds_sync();
+            const int nx = it + p + WS_PD;
+            if (nx < nch) {
+                ws_fetch(sg.a, sg.lda, ca, sg.avalid, k0 + 16 * nx, sg.ca, ra[p]);
+                ws_fetch(sg.b, sg.ldb, cb, 32, k0 + 16 * nx, sg.cb, rb[p]);
+            }
+            ws_mma16(acc, sA, sB);
+        }
+    }
+#pragma unroll
+    for (int p = 0; p < WS_PD; ++p) {
+        if (it + p < nch) {
+            wave_lds_sync();
+            ws_stash(sA, ca, ra[p]);
+            ws_stash(sB, cb, rb[p]);
+            wave_lds_sync();
+            ws_mma16(acc, sA, sB);
         }
     }
     wave_lds_sync();

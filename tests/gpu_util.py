@@ -89,3 +89,35 @@ def sigma_error(St, lay, S):
 def logdet_error(logdet, f):
     # scale: sum_j |2 log L_jj| (= |log det| when every pivot is >= 1), floored at 1
     return abs(logdet - f.logdet) / max(1.0, float(np.sum(np.abs(2.0 * np.log(f.diag())))))
+
+
+def column_errors(Lt, St, lay, f, M, oracle_mod, j):
+    """Column j of L and of Sigma, as stored in the tile buffers Lt and St,
+    against the oracle: (L error, largest stored L entry outside the element
+    band, Sigma error, rows checked).
+
+    L_ij is scaled by sqrt(A_ii).  Sigma_ij is scaled by sqrt(Sigma_jj / A_ii):
+    1 / A_ii is a lower bound of Sigma_ii for SPD A, so this is at least as
+    strict as the correlation scale sqrt(Sigma_ii Sigma_jj)."""
+    nb, w = lay.nb, f.w
+    Adiag = np.concatenate([M.ab[0], np.diag(M.C)]) if lay.arrow else M.ab[0]
+    rows, vals = lo.lower_column(Lt, lay, j)
+    ref = np.zeros_like(vals)
+    inband = np.ones(len(rows), dtype=bool)
+    for k, i in enumerate(rows):
+        if j < nb and i < nb:
+            if i - j <= w:
+                ref[k] = f.Lr[i, w - (i - j)]
+            else:
+                inband[k] = False
+        elif j < nb:
+            ref[k] = f.LP[i - nb, j]
+        else:
+            ref[k] = f.LC[i - nb, j - nb]
+    lerr = float(np.max(np.abs(vals[inband] - ref[inband]) / np.sqrt(Adiag[rows[inband]])))
+    outside = float(np.max(np.abs(vals[~inband]))) if np.any(~inband) else 0.0
+    srows, svals = lo.lower_column(St, lay, j)
+    x = oracle_mod.sigma_column(f, j)
+    scale = np.sqrt(x[j] / Adiag[srows])
+    serr = float(np.max(np.abs(svals - x[srows]) / scale)) if np.all(np.isfinite(svals)) else float("inf")
+    return lerr, outside, serr, len(srows)
