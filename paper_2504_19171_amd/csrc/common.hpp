@@ -33,6 +33,7 @@ struct Lay {
 // Row blocks of 64 rows in an arrow tile (a_p rows, last block may be partial).
 __host__ __device__ inline int arrow_blocks(int ap) { return (ap + 63) / 64; }
 __host__ __device__ inline int imin_(int x, int y) { return x < y ? x : y; }
+__host__ __device__ inline int imax_(int x, int y) { return x > y ? x : y; }
 
 // The same pointer in every lane, held in scalar registers: lets loads use a
 // scalar base plus a 32-bit per-lane offset instead of 64-bit addresses.
@@ -41,6 +42,21 @@ __device__ inline const double* uniform_ptr(const double* p) {
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
     return (const double*)(((uint64_t)hi << 32) | lo);
+}
+
+// base[idx] for a wave-uniform base and idx < 2^29: the byte offset is a
+// 32-bit value, so the load can use the scalar-base + vector-offset form and
+// needs no 64-bit address per lane.
+__device__ inline double ld_s(const double* base, uint32_t idx) {
+    uint32_t o = idx << 3;
+    asm volatile("" : "+v"(o));   // keep the 64-bit address out of loop-invariant code motion
+    return *(const double*)((const char*)base + o);
+}
+
+__device__ inline void st_s(double* base, uint32_t idx, double v) {
+    uint32_t o = idx << 3;
+    asm volatile("" : "+v"(o));
+    *(double*)((char*)base + o) = v;
 }
 
 // Device-coherent load / store of one double (agent-scope relaxed atomics:

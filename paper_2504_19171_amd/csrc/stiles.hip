@@ -205,6 +205,8 @@ __global__ __launch_bounds__(NT) void k_potrf3(double* M, int64_t ld, int m, dou
 // each), then the arrow tile (a_p/16 blocks).  Wavefront w owns columns
 // 64q + 16w .. 64q + 16w + 15 of each step.
 #define TR_LD 16
+#define TR_MAXA 48   // A operands of one step per lane: (b/64 - 1) * 16 for b = 256
+__device__ inline void tr_bar_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 __global__ __launch_bounds__(NT) void k_trsm16(double* Lm, Lay L, int64_t J, const double* X64, int g0) {
     __shared__ double sR[256 * TR_LD];   // R, [column][row]
     __shared__ double sZ[64 * TR_LD];    // Z of the current step, [column][row]
@@ -214,48 +216,67 @@ __global__ __launch_bounds__(NT) void k_trsm16(double* Lm, Lay L, int64_t J, con
     int ld;
     if (g < s * nbr) { C = Lm + L.band(J, 1 + g / nbr) + (g % nbr) * 16; ld = L.b; }
     else { C = Lm + L.arrow(J) + (g - s * nbr) * 16; ld = L.ap; }
-    const double* Ljj = Lm + L.band(J, 0);
+    C = (double*)uniform_ptr(C);
+    const double* Ljj = uniform_ptr(Lm + L.band(J, 0));
+    const double* Xb = uniform_ptr(X64);
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int b = L.b;
     const int nq = b / 64;
+    const int KX = 16 * (w + 1);
+    // operands of step 0 (C tile and X64 rows; no A operands yet)
+    dbl4 cn;
+    double xn[16];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cn[r] = ld_s(C, (uint32_t)(li + (16 * w + 4 * r + lk) * ld));
+#pragma unroll
+    for (int t = 0; t < 16; ++t) xn[t] = ld_s(Xb, (uint32_t)((16 * w + li) + (4 * t + lk) * 64));
     for (int q = 0; q < nq; ++q) {
         const int c0 = 64 * q + 16 * w;
-        // Z^T tile (columns c0.., all 16 rows): element r = Z^T[4r + lk][li] = Z[li][c0 + 4r + lk]
-        dbl4 a0, a1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int r = 0; r < 4; ++r) a0[r] = C[li + (int64_t)(c0 + 4 * r + lk) * ld];
         const int K = 64 * q;
-        for (int k = 0; k < K; k += 8) {
-            const double av0 = -Ljj[(c0 + li) + (int64_t)(k + lk) * b];
-            const double bv0 = sR[(k + lk) * TR_LD + li];
-            const double av1 = -Ljj[(c0 + li) + (int64_t)(k + 4 + lk) * b];
-            const double bv1 = sR[(k + 4 + lk) * TR_LD + li];
-            a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av0, bv0, a0, 0, 0, 0);
-            a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av1, bv1, a1, 0, 0, 0);
+        // Z^T tile (columns c0.., all 16 rows): element r = Z^T[4r + lk][li] = Z[li][c0 + 4r + lk]
+        dbl4 a0 = cn, a1 = {0.0, 0.0, 0.0, 0.0};
+        double xv[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) xv[t] = xn[t];
+        double av[TR_MAXA];
+#pragma unroll
+        for (int t = 0; t < TR_MAXA; ++t)
+            av[t] = -ld_s(Ljj, (uint32_t)((c0 + li) + imin_(4 * t + lk, b - 1) * b));
+        // next step's C tile and X64 rows go out now
+        if (q + 1 < nq) {
+            const int c1 = c0 + 64;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) cn[r] = ld_s(C, (uint32_t)(li + (c1 + 4 * r + lk) * ld));
+#pragma unroll
+            for (int t = 0; t < 16; ++t) xn[t] = ld_s(Xb, (uint32_t)((q + 1) * 4096 + (16 * w + li) + (4 * t + lk) * 64));
+        }
+#pragma unroll
+        for (int t = 0; t < TR_MAXA; t += 2) {
+            if (4 * t < K) {
+                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], sR[(4 * t + lk) * TR_LD + li], a0, 0, 0, 0);
+                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t + 1], sR[(4 * t + 4 + lk) * TR_LD + li], a1, 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) sZ[(16 * w + 4 * r + lk) * TR_LD + li] = a0[r] + a1[r];
-        __syncthreads();
+        tr_bar_lds();
         // R^T rows 16w.. of block q = X64_q(rows 16w..) Z^T; X64 is lower triangular
-        const double* Xq = X64 + (int64_t)q * 4096;
         dbl4 o0 = {0.0, 0.0, 0.0, 0.0}, o1 = {0.0, 0.0, 0.0, 0.0};
-        const int KX = 16 * (w + 1);
-        for (int k = 0; k < KX; k += 8) {
-            const double av0 = Xq[(16 * w + li) + (k + lk) * 64];
-            const double bv0 = sZ[(k + lk) * TR_LD + li];
-            o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av0, bv0, o0, 0, 0, 0);
-            const double av1 = Xq[(16 * w + li) + (k + 4 + lk) * 64];
-            const double bv1 = sZ[(k + 4 + lk) * TR_LD + li];
-            o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av1, bv1, o1, 0, 0, 0);
+#pragma unroll
+        for (int t = 0; t < 16; t += 2) {
+            if (4 * t < KX) {
+                o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[t], sZ[(4 * t + lk) * TR_LD + li], o0, 0, 0, 0);
+                o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[t + 1], sZ[(4 * t + 4 + lk) * TR_LD + li], o1, 0, 0, 0);
+            }
         }
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             const double v = o0[r] + o1[r];
             sR[(c0 + 4 * r + lk) * TR_LD + li] = v;
-            C[li + (int64_t)(c0 + 4 * r + lk) * ld] = v;
+            st_s(C, (uint32_t)(li + (c0 + 4 * r + lk) * ld), v);
         }
-        __syncthreads();
+        tr_bar_lds();   // sR and sZ reuse; the stores to C are read by no one here
     }
 }
 
@@ -325,13 +346,21 @@ __global__ __launch_bounds__(NT) void k_update32(double* Lm, Lay L, int64_t J, i
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // the output block is read now, so its round trip overlaps the products
+    double ov[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q, i = e & 31, j = e >> 5;
+        ov[q] = (i < va && j < vb) ? O[i + (int64_t)j * ldo] : 0.0;
+    }
     // B(k, j) = L_cols[j][k]: the transposed access of the column rows
     const Seg sg = mkseg(Ap, lda, 0, Bp, ldb, 1, L.b, va);
     wave_segs(acc, 1, L.b, smem, [&](int) { return sg; });
     wave_reduce(acc, smem, red);
-    for (int e = threadIdx.x; e < 1024; e += 256) {
-        const int i = e & 31, j = e >> 5;
-        if (i < va && j < vb) O[i + (int64_t)j * ldo] -= red[j * WR_LD + i];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q, i = e & 31, j = e >> 5;
+        if (i < va && j < vb) O[i + (int64_t)j * ldo] = ov[q] - red[j * WR_LD + i];
     }
 }
 
@@ -615,6 +644,25 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
         nseg = (kind == P2_DA) ? far + (L.ap > 0 ? 1 : 0) : 1;
         ktot = (kind == P2_DA) ? far * L.b + L.ap : L.b;
     }
+    double* O;
+    int64_t ldo;
+    int mv = 32;
+    if (rowtask) {
+        if (d != ARW) { O = p.S + L.band(J, d) + rbl * 32 + (int64_t)cb * 32 * L.b; ldo = L.b; }
+        else { O = p.S + L.arrow(J) + rbl * 32 + (int64_t)cb * 32 * L.ap; ldo = L.ap; mv = imin_(32, L.ap - rbl * 32); }
+    } else {
+        O = p.S + L.band(J, 0) + rb * 32 + (int64_t)cb * 32 * L.b;
+        ldo = L.b;
+    }
+    const bool diag = (kind >= P2_DA) && rb == cb;
+    // the partial already stored (L, L1, DB) is final once the task runs:
+    // read it now so its round trip overlaps the products
+    double ov[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q, i = e & 31, j = e >> 5;
+        ov[q] = (kfar || i >= mv || (diag && i < j)) ? 0.0 : ld_coh(O + i + (int64_t)j * ldo);
+    }
     dbl4 acc[2][2];
 #pragma unroll
     for (int i = 0; i < 2; ++i)
@@ -636,28 +684,17 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
         return mkseg(p.W + L.arrow(J) + (int64_t)rb * 32 * L.ap, L.ap, 1,
                      p.S + L.arrow(J) + (int64_t)cb * 32 * L.ap, L.ap, 0, L.ap, 32, 0, 1);
     });
-    double* O;
-    int64_t ldo;
-    int mv = 32;
-    if (rowtask) {
-        if (d != ARW) { O = p.S + L.band(J, d) + rbl * 32 + (int64_t)cb * 32 * L.b; ldo = L.b; }
-        else { O = p.S + L.arrow(J) + rbl * 32 + (int64_t)cb * 32 * L.ap; ldo = L.ap; mv = imin_(32, L.ap - rbl * 32); }
-    } else {
-        O = p.S + L.band(J, 0) + rb * 32 + (int64_t)cb * 32 * L.b;
-        ldo = L.b;
-    }
     TRACE(t, 4, wall_clock64());
     wave_reduce(acc, smem, red);
     TRACE(t, 5, wall_clock64());
     // out = base - red, base = the partial already stored (L, L1, DB),
     // Sigma_JJ's initial value X^T X (DA), or 0 (E, E1)
     const bool mirror = (kind == P2_DB) || (kind == P2_DA && mirror_da);
-    const bool diag = (kind >= P2_DA) && rb == cb;
-    for (int e = threadIdx.x; e < 1024; e += 256) {
-        const int i = e & 31, j = e >> 5;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int e = threadIdx.x + 256 * q, i = e & 31, j = e >> 5;
         if (i >= mv || (diag && i < j)) continue;
-        const double base = kfar ? 0.0 : ld_coh(O + i + (int64_t)j * ldo);
-        red[j * WR_LD + i] = base - red[j * WR_LD + i];
+        red[j * WR_LD + i] = ov[q] - red[j * WR_LD + i];
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 1024; e += 256) {
@@ -868,12 +905,15 @@ static int grid_for(int64_t work) {
     return (int)g;
 }
 
-// Second stream (default priority) and events of the factor pipeline, one set
-// per device, created on first use.  The mutex serialises the enqueue of
-// concurrent factor calls on one device (their kernels may still overlap).
+// Two internal streams (default priority) and the events of the factor
+// pipeline, one set per device, created on first use: the caller's stream
+// forks into them and joins them back.  Running the chain on an internal
+// stream rather than the caller's keeps the overlap when the caller uses the
+// legacy default stream.  The mutex serialises the enqueue of concurrent
+// factor calls on one device (their kernels may still overlap).
 struct Side {
-    hipStream_t s = nullptr;
-    hipEvent_t fork = nullptr, po = nullptr, tr = nullptr, up = nullptr, join = nullptr;
+    hipStream_t a = nullptr, b = nullptr;
+    hipEvent_t fork = nullptr, po = nullptr, tr = nullptr, up = nullptr, ja = nullptr, jb = nullptr;
     std::mutex mu;
 };
 static Side g_side[64];
@@ -883,13 +923,27 @@ static int side_get(Side** out) {
     if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return STILES_EHIP;
     Side& sd = g_side[d];
     std::lock_guard<std::mutex> g(g_dmu);
-    if (!sd.s) {
-        hipStream_t s;
-        if (hipStreamCreateWithFlags(&s, hipStreamNonBlocking) != hipSuccess) return STILES_EHIP;
-        hipEvent_t* ev[5] = {&sd.fork, &sd.po, &sd.tr, &sd.up, &sd.join};
+    if (!sd.b) {
+        hipStream_t a, b;
+        if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess) return STILES_EHIP;
+        // STILES_RESERVE_CUS=r keeps the off-chain stream off the first r
+        // compute units, so the chain never waits for a free unit.
+        int reserve = 0;
+        if (const char* e = getenv("STILES_RESERVE_CUS")) reserve = atoi(e);
+        int cus = 0;
+        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess) return STILES_EHIP;
+        if (reserve > 0 && reserve < cus) {
+            std::vector<uint32_t> mask((cus + 31) / 32, 0u);
+            for (int c = reserve; c < cus; ++c) mask[c / 32] |= 1u << (c % 32);
+            if (hipExtStreamCreateWithCUMask(&b, (uint32_t)mask.size(), mask.data()) != hipSuccess) return STILES_EHIP;
+        } else if (hipStreamCreateWithFlags(&b, hipStreamNonBlocking) != hipSuccess) {
+            return STILES_EHIP;
+        }
+        hipEvent_t* ev[6] = {&sd.fork, &sd.po, &sd.tr, &sd.up, &sd.ja, &sd.jb};
         for (auto e : ev)
             if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return STILES_EHIP;
-        sd.s = s;
+        sd.a = a;
+        sd.b = b;
     }
     *out = &sd;
     return 0;
@@ -1019,7 +1073,7 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     Side* sd;
     if (side_get(&sd)) return STILES_EHIP;
     std::lock_guard<std::mutex> lk(sd->mu);
-    hipStream_t sb = sd->s;
+    hipStream_t sa = sd->a, sb = sd->b;
 
     if (A != Lm) {
         hipEvent_t tm = tm_begin(st);
@@ -1027,12 +1081,13 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
         tm_end(tm, STILES_TK_OTHER, st);
     }
     LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, winfo, 0x7fffffff);
-    // Two streams.  The caller's stream carries the dependency chain of the
-    // diagonal tiles: POTRF(J) -> TRSM of tile (J+1, J) -> its SYRK into
-    // (J+1, J+1) -> POTRF(J+1).  The side stream carries the rest of column
-    // J (TRSM of the other rows, the other trailing updates), which overlaps
-    // the next steps of the chain.
+    // Two streams.  Stream a carries the dependency chain of the diagonal
+    // tiles: POTRF(J) -> TRSM of tile (J+1, J) -> its SYRK into (J+1, J+1)
+    // -> POTRF(J+1).  Stream b carries the rest of column J (TRSM of the
+    // other rows, the other trailing updates), which overlaps the next steps
+    // of the chain.
     HIPCHK(hipEventRecord(sd->fork, st));
+    HIPCHK(hipStreamWaitEvent(sa, sd->fork, 0));
     HIPCHK(hipStreamWaitEvent(sb, sd->fork, 0));
     const size_t po_smem = sizeof(double) * potrf_smem_doubles(L.b);
     const int nbr = L.b / 16, C32 = L.b / 32;
@@ -1040,21 +1095,21 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
         const int s = L.s(J);
         double* Xj = X64 + J * x64_per;
         if (g_potrf_kind == 1)
-            LAUNCH(STILES_TK_POTRF, k_potrf_x64, dim3(1), dim3(NT), po_smem, st, Lm + L.band(J, 0), (int64_t)L.b, L.b,
+            LAUNCH(STILES_TK_POTRF, k_potrf_x64, dim3(1), dim3(NT), po_smem, sa, Lm + L.band(J, 0), (int64_t)L.b, L.b,
                    Xj, ldp + 2 * J, winfo, J * (int64_t)L.b);
         else
-            LAUNCH(STILES_TK_POTRF, k_potrf3, dim3(1), dim3(NT), 0, st, Lm + L.band(J, 0), (int64_t)L.b, L.b, Xj,
+            LAUNCH(STILES_TK_POTRF, k_potrf3, dim3(1), dim3(NT), 0, sa, Lm + L.band(J, 0), (int64_t)L.b, L.b, Xj,
                    ldp + 2 * J, winfo, J * (int64_t)L.b);
-        HIPCHK(hipEventRecord(sd->po, st));
+        HIPCHK(hipEventRecord(sd->po, sa));
         const int tr_crit = s >= 1 ? nbr : 0;
         const int tr_all = s * nbr + L.ap / 16;
         const int up_crit = s >= 1 ? C32 * (C32 + 1) / 2 : 0;
         const int up_all = upd32_count(L, J);
         if (tr_crit > 0) {
-            if (J > 0) HIPCHK(hipStreamWaitEvent(st, sd->up, 0));   // updates of column J-1 into tile (J+1, J)
-            LAUNCH(STILES_TK_TRSM, k_trsm16, dim3(tr_crit), dim3(NT), 0, st, Lm, L, J, (const double*)Xj, 0);
-            HIPCHK(hipEventRecord(sd->tr, st));
-            LAUNCH(STILES_TK_UPDATE, k_update32, dim3(up_crit), dim3(NT), 0, st, Lm, L, J, 0);
+            if (J > 0) HIPCHK(hipStreamWaitEvent(sa, sd->up, 0));   // updates of column J-1 into tile (J+1, J)
+            LAUNCH(STILES_TK_TRSM, k_trsm16, dim3(tr_crit), dim3(NT), 0, sa, Lm, L, J, (const double*)Xj, 0);
+            HIPCHK(hipEventRecord(sd->tr, sa));
+            LAUNCH(STILES_TK_UPDATE, k_update32, dim3(up_crit), dim3(NT), 0, sa, Lm, L, J, 0);
         }
         HIPCHK(hipStreamWaitEvent(sb, sd->po, 0));
         if (tr_all > tr_crit)
@@ -1065,8 +1120,10 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
             LAUNCH(STILES_TK_UPDATE, k_update32, dim3(up_all - up_crit), dim3(NT), 0, sb, Lm, L, J, up_crit);
         HIPCHK(hipEventRecord(sd->up, sb));
     }
-    HIPCHK(hipEventRecord(sd->join, sb));
-    HIPCHK(hipStreamWaitEvent(st, sd->join, 0));
+    HIPCHK(hipEventRecord(sd->ja, sa));
+    HIPCHK(hipEventRecord(sd->jb, sb));
+    HIPCHK(hipStreamWaitEvent(st, sd->ja, 0));
+    HIPCHK(hipStreamWaitEvent(st, sd->jb, 0));
     int nparts = (int)L.nt;
     if (L.ap > 0) {
         double* Cc = Lm + L.corner();

@@ -91,7 +91,7 @@ __device__ inline void ws_stash(double* s, int contig_x, const double r[8]) {
     }
 }
 
-#define WS_PD 3   // 16-deep chunks in flight per wavefront (registers)
+#define WS_PD 2   // 16-deep chunks in flight per wavefront (registers)
 
 __device__ inline void ws_mma16(dbl4 (&acc)[2][2], const double* sA, const double* sB) {
     const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
