@@ -15,6 +15,11 @@ HIPCC_FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-shared",
     # packed FP32 instructions stay off in every HIP build of this project
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary VGPRs: without this the compiler puts
+    # them in AGPRs whenever a kernel may use more than 256 registers, and a
+    # loop that also reads its accumulators with vector instructions copies
+    # them across every iteration
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-I", os.path.join(ROOT, "include"),
 ]
 

@@ -19,6 +19,7 @@
 
 #define P3_LD 17
 #define P3_SLOTS 5   // row tiles I >= 1 per wavefront: 15 / 3
+#define P3_POOL 65   // 16 x 16 tiles of L alive at once at m = 256 (checked by p3_make_slots)
 
 struct P3Smem {
     double D[16 * P3_LD];          // diagonal block of the current panel, D(i, j) at D[j * P3_LD + i]
@@ -26,9 +27,9 @@ struct P3Smem {
     double S22[8 * 9];             // factor16 scratch: S(i, j) at S22[i * 9 + j]
     double T[8 * 9];               // T = L21 Y11, T(i, j) at T[i * 9 + j]
     double Dn[2][16 * P3_LD];      // next diagonal blocks (by parity), reduced up to two panels back
-    double Pn[2][16][256];         // L tiles of solved panels by parity: L[16I + i][c0 + j] at Pn[par][I][j * 16 + i]
-    double Cp[16][256];            // reduced current panel, transposed MFMA form (r * 64 + lane)
-                                   // (Pn and Cp, 48 tiles, are the epilogue's staging area)
+    double pool[P3_POOL][256];     // tiles (I, k) of L in slots given by p3_slot: first the reduced tile in
+                                   // transposed MFMA form (r * 64 + lane), then, solved in place,
+                                   // L[16I + i][16k + j] at [j * 16 + i]  (also the epilogue's staging area)
     double dg[256];                // diagonal of L, then 2 log L_jj
     double ps[64], pc[64];         // log det partial sums
     double lsum, lcomp;
@@ -91,12 +92,10 @@ __device__ inline void p3_inv8(double (&a)[36], const double (&rinv)[8]) {
     }
 }
 
-// Workgroup barriers that wait only for what the next phase reads: LDS
-// (lgkm) always, global stores (vm) only where another wavefront reads them
-// back from global memory.  The "memory" clobber keeps the compiler from
-// moving accesses across them.
+// Workgroup barrier that waits only for LDS traffic (the phases exchange
+// data through LDS alone; global stores stay in flight until the epilogue).
+// The "memory" clobber keeps the compiler from moving accesses across it.
 __device__ inline void p3_bar_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-__device__ inline void p3_bar_all() { asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 __device__ inline void p3_wsync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -275,88 +274,202 @@ __device__ inline void p3_inv64(const double* Mc, int ldi, double* X64, int m, d
     block(3, 2, L32, L32, Y[2], nullptr, nullptr, nullptr, nullptr);        // X32
 }
 
-// Tiles I = 3s + w (slots s >= S0) of panel p+2 (columns c0 + 32 ..) reduced
-// over the panels < p, read from global memory in 16-column chunks: the
-// raw tile values go into nxt, the products are accumulated apart and
-// subtracted at the end.  The next chunk is in flight while the current one
-// is multiplied; all loads are unconditional (a chunk past the end re-reads
-// the last one and is not used) so the waits stay exact.
+// Slots of the 16 x 16 tiles of L in the LDS pool, for np = 4, 8, 12, 16 row
+// tiles.  Tile (I, k), I > k, enters the pool as a reduced tile of panel k
+// during U(k-1) (the prologue for k = 0), is solved in place at S(k), and is
+// read for the last time in U(I-2) (in U(I-1) when I = k+1; see potrf3).  A
+// slot given back at the end of one U phase is handed out again from the next
+// one on.  The table is packed one dword per lane for p3_slot: byte I/4 of
+// lane 16 (I % 4) + k.
+struct P3SlotPack {
+    uint32_t w[4][64];
+    int peak[4];
+};
+constexpr P3SlotPack p3_make_slots() {
+    P3SlotPack t{};
+    for (int v = 0; v < 4; ++v) {
+        const int np = 4 * (v + 1);
+        int slot[16][16] = {};
+        int fr[P3_POOL] = {};
+        int nf = 0, live = 0, peak = 0;
+        for (int q = P3_POOL - 1; q >= 0; --q) fr[nf++] = q;
+        // an empty free list makes fr[-1] below, which stops the compilation
+        for (int I = 1; I < np; ++I) { slot[I][0] = fr[--nf]; ++live; }
+        peak = live;
+        for (int p = 0; p + 1 < np; ++p) {
+            for (int I = p + 2; I < np; ++I) { slot[I][p + 1] = fr[--nf]; ++live; }
+            if (live > peak) peak = live;
+            if (p + 2 < np)
+                for (int k = 0; k <= p; ++k) { fr[nf++] = slot[p + 2][k]; --live; }
+            fr[nf++] = slot[p + 1][p];
+            --live;
+        }
+        for (int I = 0; I < 16; ++I)
+            for (int k = 0; k < 16; ++k) t.w[v][16 * (I & 3) + k] |= (uint32_t)slot[I][k] << (8 * (I >> 2));
+        t.peak[v] = peak;
+    }
+    return t;
+}
+constexpr P3SlotPack kP3Slots = p3_make_slots();
+static_assert(kP3Slots.peak[3] == P3_POOL && kP3Slots.peak[2] <= P3_POOL, "pool size");
+__device__ const P3SlotPack p3_slot_pack = kP3Slots;
+
+// Slot of tile (I, k); tab is this lane's dword of the packed table (I, k uniform).
+__device__ inline int p3_slot(uint32_t tab, int I, int k) {
+    const uint32_t v = (uint32_t)__builtin_amdgcn_readlane((int)tab, ((I & 3) << 4) | k);
+    return (int)((v >> ((I >> 2) << 3)) & 0xffu);
+}
+
+// The panel wavefronts' work in the phases of potrf3, for the slots s >= S0
+// (tiles I = 3s + w): every slot runs the same instructions, so there is one
+// basic block per step whatever the slot count; a slot past the last tile
+// (I >= np) works on a clamped copy, and a slot with nothing to do works on
+// whatever its indices give, and neither stores anything.
+
+// S(p): L_Ip^T = Y C_Ip^T for the tiles I > p, in place in the pool (each
+// tile read whole before it is written) and to global memory.
 template <int S0>
-__device__ __forceinline__ void p3_reduce_panel(dbl4 (&nxt)[P3_SLOTS], const double* Mc, int ldi, int w, int np,
-                                                int c0, int li, int lk) {
+__device__ __forceinline__ void p3_solve_slots(P3Smem& sm, double* Mw, int ldi, uint32_t tab, int w, int np, int p,
+                                               int lane, int li, int lk) {
     constexpr int NS = P3_SLOTS - S0;
-    const int c2 = c0 + 32;
+    const int c0 = 16 * p;
+    double* X[NS];
+    dbl4 o[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
-        const int I = imin_(3 * (S0 + q) + w, np - 1);
-#pragma unroll
-        for (int r = 0; r < 4; ++r) nxt[S0 + q][r] = ld_s(Mc, (uint32_t)((16 * I + li) + (c2 + 4 * r + lk) * ldi));
+        X[q] = sm.pool[p3_slot(tab, imin_(3 * (S0 + q) + w, np - 1), p)];
+        o[q] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
-    if (c0 == 0) return;
-    dbl4 red[NS];
+    double yv[4];
 #pragma unroll
-    for (int q = 0; q < NS; ++q) red[q] = dbl4{0.0, 0.0, 0.0, 0.0};
-    auto fetch = [&](double (&ra)[4], double (&rb)[NS][4], int k0) {
+    for (int r = 0; r < 4; ++r) yv[r] = sm.Y[li * P3_LD + 4 * r + lk];
 #pragma unroll
-        for (int kk = 0; kk < 4; ++kk) ra[kk] = ld_s(Mc, (uint32_t)((c2 + li) + (k0 + 4 * kk + lk) * ldi));
+    for (int r = 0; r < 4; ++r)
 #pragma unroll
-        for (int q = 0; q < NS; ++q) {
-            const int I = imin_(3 * (S0 + q) + w, np - 1);
+        for (int q = 0; q < NS; ++q) o[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[r], X[q][r * 64 + lane], o[q], 0, 0, 0);
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk) rb[q][kk] = ld_s(Mc, (uint32_t)((16 * I + li) + (k0 + 4 * kk + lk) * ldi));
+    for (int q = 0; q < NS; ++q) {
+        const int I = 3 * (S0 + q) + w;
+        if (I > p && I < np) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                st_s(Mw, (uint32_t)((16 * I + li) + (c0 + 4 * r + lk) * ldi), o[q][r]);
+                X[q][(4 * r + lk) * 16 + li] = o[q][r];
+            }
         }
-    };
-    auto mma = [&](const double (&ra)[4], const double (&rb)[NS][4]) {
+    }
+}
+
+// U(p), p + 2 < np: panel p into the tiles I >= p+2 of panel p+1 (nxt ->
+// pool, transposed MFMA form, for S(p+1)); then the tiles I >= p+2 of panel
+// p+2: raw values from global memory into nxt (the only global reads of the
+// loop, in flight during the products), reduced over the panels 0..p from the
+// pool (products accumulated apart, subtracted at the end).  The panels go in
+// pairs (a lone first panel when their count is odd), so the loop body is one
+// basic block; the owner of tile p+2 hands its diagonal block to wavefront 0
+// through Dn.
+template <int S0>
+__device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& sm, const double* Mc, int ldi,
+                                                uint32_t tab, int w, int np, int p, int lane, int li, int lk) {
+    constexpr int NS = P3_SLOTS - S0;
+    const int c2 = 16 * (p + 2);
+    const int lo = lk * 16 + li;
+    int Is[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) Is[q] = imin_(3 * (S0 + q) + w, np - 1);
+    {
+        const double* L1 = sm.pool[p3_slot(tab, p + 1, p)];
+        double av[4];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) av[kk] = -L1[64 * kk + lo];
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
-            for (int q = 0; q < NS; ++q) red[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(ra[kk], rb[q][kk], red[q], 0, 0, 0);
-    };
-    double ra0[4], ra1[4], rb0[NS][4], rb1[NS][4];
-    if (NS <= 3) {
-        // two chunks in flight: chunk 3t in buffer 0, 3t+1 in 1, 3t+2 in 2
-        double ra2[4], rb2[NS][4];
-        fetch(ra0, rb0, 0);
-        fetch(ra1, rb1, imin_(16, c0 - 16));
-        for (int k0 = 0; k0 < c0; k0 += 48) {
-            fetch(ra2, rb2, imin_(k0 + 32, c0 - 16));
-            mma(ra0, rb0);
-            fetch(ra0, rb0, imin_(k0 + 48, c0 - 16));
-            if (k0 + 16 < c0) mma(ra1, rb1);
-            fetch(ra1, rb1, imin_(k0 + 64, c0 - 16));
-            if (k0 + 32 < c0) mma(ra2, rb2);
-        }
-    } else {
-        // one chunk in flight
-        fetch(ra0, rb0, 0);
-        for (int k0 = 0; k0 < c0; k0 += 32) {
-            fetch(ra1, rb1, imin_(k0 + 16, c0 - 16));
-            mma(ra0, rb0);
-            fetch(ra0, rb0, imin_(k0 + 32, c0 - 16));
-            if (k0 + 16 < c0) mma(ra1, rb1);
+            for (int q = 0; q < NS; ++q)
+                nxt[S0 + q] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[kk], sm.pool[p3_slot(tab, Is[q], p)][64 * kk + lo],
+                                                                   nxt[S0 + q], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int I = 3 * (S0 + q) + w;
+            if (I >= p + 2 && I < np) {
+                double* X = sm.pool[p3_slot(tab, I, p + 1)];
+#pragma unroll
+                for (int r = 0; r < 4; ++r) X[r * 64 + lane] = nxt[S0 + q][r];
+            }
         }
     }
 #pragma unroll
-    for (int q = 0; q < NS; ++q) nxt[S0 + q] -= red[q];
+    for (int q = 0; q < NS; ++q)
+#pragma unroll
+        for (int r = 0; r < 4; ++r) nxt[S0 + q][r] = ld_s(Mc, (uint32_t)((16 * Is[q] + li) + (c2 + 4 * r + lk) * ldi));
+    dbl4 red[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) red[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+    // operands of panel k (clamped to p: a fetch past the end is not used)
+    auto fetch = [&](double (&a)[4], double (&bq)[NS][4], int k) {
+        k = imin_(k, p);
+        const double* A = sm.pool[p3_slot(tab, p + 2, k)];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) a[kk] = A[64 * kk + lo];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const double* B = sm.pool[p3_slot(tab, Is[q], k)];
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) bq[q][kk] = B[64 * kk + lo];
+        }
+    };
+    auto mma = [&](const double (&a)[4], const double (&bq)[NS][4]) {
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int q = 0; q < NS; ++q) red[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[kk], bq[q][kk], red[q], 0, 0, 0);
+    };
+    double a0[4], a1[4], b0[NS][4], b1[NS][4];
+    int k0 = 0;
+    fetch(a0, b0, 0);
+    if ((p & 1) == 0) {   // an odd panel count: panel 0 alone first
+        mma(a0, b0);
+        fetch(a0, b0, 1);
+        k0 = 1;
+    }
+    fetch(a1, b1, k0 + 1);
+    for (int k = k0; k <= p; k += 2) {
+        mma(a0, b0);
+        fetch(a0, b0, k + 2);
+        mma(a1, b1);
+        fetch(a1, b1, k + 3);
+    }
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        nxt[S0 + q] -= red[q];
+        if (3 * (S0 + q) + w == p + 2) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.Dn[(p + 2) & 1][(4 * r + lk) * P3_LD + li] = nxt[S0 + q][r];
+        }
+    }
 }
 
 // In-place Cholesky of the m x m lower triangle of M (column-major, leading
-// dimension ld), m a multiple of 64, m <= 256; the strict upper triangle is
-// set to 0.  X64 + q*4096: inverse of the q-th 64 x 64 diagonal block of L
+// dimension ld), m a multiple of 64, m <= 256; zeros go only into the upper
+// parts of the diagonal 16 x 16 blocks (the rest of the strict upper triangle
+// is left as it is, for the caller to clear off the dependency chain).
+// X64 + q*4096: inverse of the q-th 64 x 64 diagonal block of L
 // (column-major, entries above its 16 x 16 block diagonal not written).
 // Thread 0 returns the first failing local column (or -1) and the log det
 // pair.
 //
 // Software pipeline over the 16-column panels p, two phases per panel:
 //   S(p): L_pp and Y_pp go out; wavefronts 1..3 solve their tiles of panel p
-//         (L_Ip = C_Ip Y^T) into LDS (Pn, by parity of p) and global memory;
+//         (L_Ip = C_Ip Y^T) in place in the LDS pool and to global memory;
 //   U(p): wavefront 0 forms the next diagonal block D_{p+1} = Dn - L_{p+1,p}
 //         L_{p+1,p}^T and factors it (factor16), while wavefronts 1..3 add
-//         panel p into the tiles of panel p+1 (-> Cp, read by S(p+1)) and
-//         reduce the tiles of panel p+2 over panels 0..p (older panels from
-//         global memory, panel p from LDS); the owner of tile p+2 hands its
-//         diagonal block to wavefront 0 through Dn (by parity).
-// So the chain of diagonal factorizations overlaps all the other work.
+//         panel p into the tiles of panel p+1 (into the pool, solved by
+//         S(p+1)) and reduce the tiles of panel p+2 over panels 0..p; the
+//         owner of tile p+2 hands its diagonal block to wavefront 0 through Dn
+//         (by parity).
+// Every tile of L stays in the LDS pool from its reduction to its last use,
+// so global memory is read only for the raw tiles, each once.  The chain of
+// diagonal factorizations overlaps all the other work.
 __device__ inline void potrf3(double* M, int64_t ld, int m, double* X64, P3Smem& sm, int* fail_out, double* ls_out,
                               double* lc_out) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -366,7 +479,8 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* X64, P3Smem&
     double* Mw = (double*)Mc;
     const int ldi = (int)ld;
     int fail = -1;
-    // panel 0 into LDS, transposed MFMA form: Cp[I][r*64 + lane] = C[16I + li][4r + lk];
+    const uint32_t tab = p3_slot_pack.w[np / 4 - 1][lane];
+    // panel 0 into the pool, transposed MFMA form: [r*64 + lane] = C[16I + li][4r + lk];
     // D_0 = tile (0, 0); Y's upper part stays 0 from here on
     {
         double v[16];
@@ -375,8 +489,8 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* X64, P3Smem&
         for (int I = 0; I < 16; ++I)
             v[I] = ld_s(Mc, (uint32_t)((16 * imin_(I, np - 1) + (ln & 15)) + (4 * r + (ln >> 4)) * ldi));
 #pragma unroll
-        for (int I = 0; I < 16; ++I)
-            if (I < np) sm.Cp[I][q] = v[I];
+        for (int I = 1; I < 16; ++I)
+            if (I < np) sm.pool[p3_slot(tab, I, 0)][q] = v[I];
     }
     {
         const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
@@ -404,110 +518,73 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* X64, P3Smem&
     p3_bar_lds();
     for (int p = 0; p < np; ++p) {
         const int c0 = 16 * p;
-        const int par = p & 1;
         // ---- S(p)
         if (w == 0) {
             double* Xg = (double*)uniform_ptr(X64 + (int64_t)(p >> 2) * 4096);
             const int xo = 16 * (p & 3);
-            for (int e = lane; e < 256; e += 64) {
-                const int i = e & 15, j = e >> 4;
-                st_s(Mw, (uint32_t)((c0 + i) + (c0 + j) * ldi), (j <= i) ? sm.D[j * P3_LD + i] : 0.0);
-                st_s(Xg, (uint32_t)((xo + i) + (xo + j) * 64), sm.Y[i * P3_LD + j]);
+            double dv[4], yv[4];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = lane & 15, j = (lane >> 4) + 4 * q;
+                dv[q] = (j <= i) ? sm.D[j * P3_LD + i] : 0.0;
+                yv[q] = sm.Y[i * P3_LD + j];
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) {
+                const int i = lane & 15, j = (lane >> 4) + 4 * q;
+                st_s(Mw, (uint32_t)((c0 + i) + (c0 + j) * ldi), dv[q]);
+                st_s(Xg, (uint32_t)((xo + i) + (xo + j) * 64), yv[q]);
             }
         } else {
-#pragma unroll
-            for (int s = 0; s < P3_SLOTS; ++s) {
-                const int I = 3 * s + w;
-                if (I > p && I < np) {
-                    dbl4 o = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        const double av = sm.Y[li * P3_LD + 4 * r + lk];
-                        o = __builtin_amdgcn_mfma_f64_16x16x4f64(av, sm.Cp[I][r * 64 + lane], o, 0, 0, 0);
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        st_s(Mw, (uint32_t)((16 * I + li) + (c0 + 4 * r + lk) * ldi), o[r]);
-                        sm.Pn[par][I][(4 * r + lk) * 16 + li] = o[r];
-                    }
-                }
+            // slots s >= s1 hold the tiles I > p
+            const int s1 = imin_(P3_SLOTS - 1, imax_(0, (p + 1 - w + 2) / 3));
+            switch (s1) {
+                case 0: p3_solve_slots<0>(sm, Mw, ldi, tab, w, np, p, lane, li, lk); break;
+                case 1: p3_solve_slots<1>(sm, Mw, ldi, tab, w, np, p, lane, li, lk); break;
+                case 2: p3_solve_slots<2>(sm, Mw, ldi, tab, w, np, p, lane, li, lk); break;
+                case 3: p3_solve_slots<3>(sm, Mw, ldi, tab, w, np, p, lane, li, lk); break;
+                default: p3_solve_slots<4>(sm, Mw, ldi, tab, w, np, p, lane, li, lk); break;
             }
         }
-        for (int j = 0; j < 16; ++j)
-            for (int i = threadIdx.x; i < c0; i += 256) st_s(Mw, (uint32_t)(i + (c0 + j) * ldi), 0.0);
-        p3_bar_lds();   // Pn[par] complete (the global stores stay in flight)
+        p3_bar_lds();   // panel p of L in the pool (the global stores stay in flight)
         if (p + 1 == np) break;
         // ---- U(p)
         if (w == 0) {
             // D_{p+1} = Dn - L_{p+1,p} L_{p+1,p}^T, then its factorization
             dbl4 acc;
+            const double* L1 = sm.pool[p3_slot(tab, p + 1, p)];
 #pragma unroll
             for (int r = 0; r < 4; ++r) acc[r] = sm.Dn[(p + 1) & 1][(4 * r + lk) * P3_LD + li];
 #pragma unroll
             for (int kk = 0; kk < 16; kk += 4) {
-                const double v = sm.Pn[par][p + 1][(kk + lk) * 16 + li];
+                const double v = L1[(kk + lk) * 16 + li];
                 acc = __builtin_amdgcn_mfma_f64_16x16x4f64(-v, v, acc, 0, 0, 0);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) sm.D[(4 * r + lk) * P3_LD + li] = acc[r];
             p3_wsync();
             p3_factor16(sm, c0 + 16, fail);
-        } else {
-            // panel p into the tiles I >= p+2 of panel p+1 -> Cp
-#pragma unroll
-            for (int s = 0; s < P3_SLOTS; ++s) {
-                const int I = 3 * s + w;
-                if (I >= p + 2 && I < np) {
-#pragma unroll
-                    for (int kk = 0; kk < 16; kk += 4) {
-                        const double av = -sm.Pn[par][p + 1][(kk + lk) * 16 + li];
-                        const double bv = sm.Pn[par][I][(kk + lk) * 16 + li];
-                        nxt[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, nxt[s], 0, 0, 0);
-                    }
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) sm.Cp[I][r * 64 + lane] = nxt[s][r];
-                }
-            }
-            // tiles I >= p+2 of panel p+2 over panels 0..p: panels < p from
-            // global memory in 16-column chunks (the next one in flight while
-            // the current one is multiplied; the rows of tile p+2 are the A
-            // operand of every slot), then panel p from LDS
-            if (p + 2 < np) {
-                // slots s >= s0 hold tiles I >= p+2; only they load and multiply
-                const int s0 = imin_(P3_SLOTS - 1, imax_(0, (p + 2 - w + 2) / 3));
-                switch (s0) {
-                    case 0: p3_reduce_panel<0>(nxt, Mc, ldi, w, np, c0, li, lk); break;
-                    case 1: p3_reduce_panel<1>(nxt, Mc, ldi, w, np, c0, li, lk); break;
-                    case 2: p3_reduce_panel<2>(nxt, Mc, ldi, w, np, c0, li, lk); break;
-                    case 3: p3_reduce_panel<3>(nxt, Mc, ldi, w, np, c0, li, lk); break;
-                    default: p3_reduce_panel<4>(nxt, Mc, ldi, w, np, c0, li, lk); break;
-                }
-#pragma unroll
-                for (int s = 0; s < P3_SLOTS; ++s) {
-                    const int I = 3 * s + w;
-                    if (I >= p + 2 && I < np) {
-#pragma unroll
-                        for (int kk = 0; kk < 16; kk += 4) {
-                            const double av = -sm.Pn[par][p + 2][(kk + lk) * 16 + li];
-                            const double bv = sm.Pn[par][I][(kk + lk) * 16 + li];
-                            nxt[s] = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, nxt[s], 0, 0, 0);
-                        }
-                        if (I == p + 2) {
-#pragma unroll
-                            for (int r = 0; r < 4; ++r) sm.Dn[(p + 2) & 1][(4 * r + lk) * P3_LD + li] = nxt[s][r];
-                        }
-                    }
-                }
+        } else if (p + 2 < np) {
+            // slots s >= s0 hold the tiles I >= p+2
+            const int s0 = imin_(P3_SLOTS - 1, imax_(0, (p + 2 - w + 2) / 3));
+            switch (s0) {
+                case 0: p3_update_slots<0>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
+                case 1: p3_update_slots<1>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
+                case 2: p3_update_slots<2>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
+                case 3: p3_update_slots<3>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
+                default: p3_update_slots<4>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
             }
         }
-        p3_bar_all();   // D, Y of p+1; Cp; Dn; the L of panel p in global memory
+        // D, Y of p+1; panel p+1 in the pool; Dn.  The global stores of L
+        // stay in flight: nothing in the loop reads them back.
+        p3_bar_lds();
     }
     __syncthreads();
     // log det: 2 log L_jj in parallel; the 64-block inverses; then a
     // fixed-order compensated sum (lane l of wavefront 0 sums entries l, l+64,
     // ..., then the lanes are joined pairwise by a butterfly)
     for (int t = threadIdx.x; t < m; t += 256) sm.dg[t] = 2.0 * log(sm.dg[t]);
-    p3_inv64(Mc, ldi, X64, m, &sm.Pn[0][0][0]);
+    p3_inv64(Mc, ldi, X64, m, &sm.pool[0][0]);
     __syncthreads();
     if (w == 0) {
         double ps = 0.0, pc = 0.0;

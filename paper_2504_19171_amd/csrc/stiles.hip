@@ -196,6 +196,17 @@ __global__ __launch_bounds__(NT) void k_potrf3(double* M, int64_t ld, int m, dou
     }
 }
 
+// Strict upper triangles of the band diagonal tiles set to 0 (the layout's
+// convention for L; k_potrf3 leaves them, as nothing in the factorization
+// reads them).  Eight workgroups per tile, b/8 columns each.
+__global__ __launch_bounds__(NT) void k_zero_upper(double* Lm, Lay L) {
+    const int64_t J = blockIdx.x >> 3;
+    const int cw = L.b / 8, c0 = (int)(blockIdx.x & 7) * cw;
+    double* T = Lm + L.band(J, 0);
+    for (int c = c0; c < c0 + cw; ++c)
+        for (int i = threadIdx.x; i < c; i += NT) T[i + (int64_t)c * L.b] = 0.0;
+}
+
 // Panel TRSM, one 16-row block per workgroup: R = C L_JJ^{-T} in place, by
 // forward substitution over the 64-column blocks q of the tile,
 //   Z_q = C_q - sum_{q' < q} R_q' L_{q,q'}^T,   R_q = Z_q X64_q^T,
@@ -1120,6 +1131,8 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
             LAUNCH(STILES_TK_UPDATE, k_update32, dim3(up_all - up_crit), dim3(NT), 0, sb, Lm, L, J, up_crit);
         HIPCHK(hipEventRecord(sd->up, sb));
     }
+    if (g_potrf_kind != 1)
+        LAUNCH(STILES_TK_OTHER, k_zero_upper, dim3((unsigned)(8 * L.nt)), dim3(NT), 0, sb, Lm, L);
     HIPCHK(hipEventRecord(sd->ja, sa));
     HIPCHK(hipEventRecord(sd->jb, sb));
     HIPCHK(hipStreamWaitEvent(st, sd->ja, 0));

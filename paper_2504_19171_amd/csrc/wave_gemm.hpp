@@ -91,7 +91,7 @@ __device__ inline void ws_stash(double* s, int contig_x, const double r[8]) {
     }
 }
 
-#define WS_PD 2   // 16-deep chunks in flight per wavefront (registers)
+#define WS_PD 2   // default number of 16-deep chunks in flight per wavefront (registers)
 
 __device__ inline void ws_mma16(dbl4 (&acc)[2][2], const double* sA, const double* sB) {
     const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
@@ -108,31 +108,32 @@ __device__ inline void ws_mma16(dbl4 (&acc)[2][2], const double* sA, const doubl
 }
 
 // acc += A(:, k0:k1) * B(k0:k1, :) for this wavefront; k0, k1 multiples of 16.
-// sw: this wavefront's LDS area (WS_WAVE_DOUBLES doubles).  Up to WS_PD
+// sw: this wavefront's LDS area (WS_WAVE_DOUBLES doubles).  Up to PD
 // chunks are being fetched while one is multiplied.
+template <int PD = WS_PD>
 __device__ inline void wave_seg(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1, double* sw) {
     const int nch = (k1 - k0) >> 4;
     if (nch <= 0) return;
     const int ca = !sg.ta, cb = sg.tb;   // A normal / B transposed: contiguous along x
     double* sA = sw;
     double* sB = sw + 16 * WS_LD;
-    double ra[WS_PD][8], rb[WS_PD][8];
+    double ra[PD][8], rb[PD][8];
 #pragma unroll
-    for (int p = 0; p < WS_PD; ++p) {
+    for (int p = 0; p < PD; ++p) {
         if (p < nch) {
             ws_fetch(sg.a, sg.lda, ca, sg.avalid, k0 + 16 * p, sg.ca, ra[p]);
             ws_fetch(sg.b, sg.ldb, cb, 32, k0 + 16 * p, sg.cb, rb[p]);
         }
     }
     int it = 0;
-    for (; it + WS_PD <= nch; it += WS_PD) {
+    for (; it + PD <= nch; it += PD) {
 #pragma unroll
-        for (int p = 0; p < WS_PD; ++p) {
+        for (int p = 0; p < PD; ++p) {
             wave_lds_sync();
             ws_stash(sA, ca, ra[p]);
             ws_stash(sB, cb, rb[p]);
             wave_lds_sync();
-            const int nx = it + p + WS_PD;
+            const int nx = it + p + PD;
             if (nx < nch) {
                 ws_fetch(sg.a, sg.lda, ca, sg.avalid, k0 + 16 * nx, sg.ca, ra[p]);
                 ws_fetch(sg.b, sg.ldb, cb, 32, k0 + 16 * nx, sg.cb, rb[p]);
@@ -141,7 +142,7 @@ __device__ inline void wave_seg(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1
         }
     }
 #pragma unroll
-    for (int p = 0; p < WS_PD; ++p) {
+    for (int p = 0; p < PD; ++p) {
         if (it + p < nch) {
             wave_lds_sync();
             ws_stash(sA, ca, ra[p]);
@@ -157,21 +158,25 @@ __device__ inline void wave_seg(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1
 // length ktot (a multiple of 16); seg(q) returns segment q.  The reduction is
 // cut at multiples of 16 into four consecutive pieces, one per wavefront.
 // smem: WS_SMEM_DOUBLES doubles.
-template <class F>
-__device__ inline void wave_segs(dbl4 (&acc)[2][2], int nseg, int ktot, double* smem, F&& seg) {
-    const int chunks = ktot >> 4;
+// Only the range [kbeg, kend) of the reduction is done when kend >= 0
+// (multiples of 16).
+template <int PD = WS_PD, class F>
+__device__ inline void wave_segs(dbl4 (&acc)[2][2], int nseg, int ktot, double* smem, F&& seg, int kbeg = 0,
+                                 int kend = -1) {
+    if (kend < 0) kend = ktot;
+    const int chunks = (kend - kbeg) >> 4;
     const int per = (chunks + 3) >> 2;
     const int w = threadIdx.x >> 6;
-    int kb = 16 * per * w, ke = 16 * per * (w + 1);
-    if (ke > ktot) ke = ktot;
-    if (kb > ktot) kb = ktot;
+    int kb = kbeg + 16 * per * w, ke = kbeg + 16 * per * (w + 1);
+    if (ke > kend) ke = kend;
+    if (kb > kend) kb = kend;
     double* sw = smem + w * WS_WAVE_DOUBLES;
     int s0 = 0;
     for (int q = 0; q < nseg && s0 < ke; ++q) {
         const Seg sg = seg(q);
         const int lo = kb > s0 ? kb : s0;
         const int hi = ke < s0 + sg.K ? ke : s0 + sg.K;
-        if (lo < hi) wave_seg(acc, sg, lo - s0, hi - s0, sw);
+        if (lo < hi) wave_seg<PD>(acc, sg, lo - s0, hi - s0, sw);
         s0 += sg.K;
     }
 }
