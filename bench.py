@@ -37,6 +37,7 @@ def kernel_flops(nb, w, a, b):
         k["update"] += m * m * b
         k["phase1"] += b ** 3 / 3 + m * b * b + b ** 3 / 3
         k["phase2"] += 2 * m * m * b + m * b * b
+        k["factor"] += b ** 3 / 3 + m * b * b + m * m * b   # one k_column launch per tile column
     k["other"] += a ** 3 / 3          # corner factor
     k["phase1"] += 2 * a ** 3 / 3     # corner TRTRI + LAUUM
     return k

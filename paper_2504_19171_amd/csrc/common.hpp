@@ -59,6 +59,19 @@ __device__ inline void st_s(double* base, uint32_t idx, double v) {
     *(double*)((char*)base + o) = v;
 }
 
+// base[idx] = v as a device-coherent store (see st_coh below), with the same
+// scalar-base + 32-bit offset addressing as st_s.
+__device__ inline void st_coh_s(double* base, uint32_t idx, double v) {
+    uint32_t o = idx << 3;
+    asm volatile("" : "+v"(o));
+    __hip_atomic_store((double*)((char*)base + o), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline double ld_coh_s(const double* base, uint32_t idx) {
+    uint32_t o = idx << 3;
+    asm volatile("" : "+v"(o));
+    return __hip_atomic_load((const double*)((const char*)base + o), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 // Device-coherent load / store of one double (agent-scope relaxed atomics:
 // they bypass the non-coherent cache levels, see persist.hpp).
 __device__ inline double ld_coh(const double* p) {

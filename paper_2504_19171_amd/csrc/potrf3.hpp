@@ -11,8 +11,9 @@
 //     wavefronts reduce the panels ahead of it (see potrf3 below);
 //   - the panel below is solved with the inverse of the diagonal block on the
 //     matrix cores, L_Ip^T = Y_pp C_Ip^T.
-// Also returns the inverses of the 64 x 64 diagonal blocks of L (for the
-// panel TRSM below the tile) and the Neumaier pair of sum 2 log L_jj.
+// Also returns the inverses of the 16 x 16 diagonal blocks of L (for the
+// panel TRSM below the tile) and the Neumaier pair of sum 2 log L_jj, and
+// announces every finished panel to a concurrent consumer (see potrf3).
 #pragma once
 #include "common.hpp"
 #include "tile_ops.hpp"
@@ -29,7 +30,7 @@ struct P3Smem {
     double Dn[2][16 * P3_LD];      // next diagonal blocks (by parity), reduced up to two panels back
     double pool[P3_POOL][256];     // tiles (I, k) of L in slots given by p3_slot: first the reduced tile in
                                    // transposed MFMA form (r * 64 + lane), then, solved in place,
-                                   // L[16I + i][16k + j] at [j * 16 + i]  (also the epilogue's staging area)
+                                   // L[16I + i][16k + j] at [j * 16 + i]
     double dg[256];                // diagonal of L, then 2 log L_jj
     double ps[64], pc[64];         // log det partial sums
     double lsum, lcomp;
@@ -92,10 +93,12 @@ __device__ inline void p3_inv8(double (&a)[36], const double (&rinv)[8]) {
     }
 }
 
-// Workgroup barrier that waits only for LDS traffic (the phases exchange
-// data through LDS alone; global stores stay in flight until the epilogue).
-// The "memory" clobber keeps the compiler from moving accesses across it.
+// Workgroup barriers: LDS traffic only (the phases exchange data through LDS
+// alone), or also every global access of every wavefront (before a panel is
+// announced).  The "memory" clobber keeps the compiler from moving accesses
+// across them.
 __device__ inline void p3_bar_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+__device__ inline void p3_bar_all() { asm volatile("s_waitcnt vmcnt(0) lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 __device__ inline void p3_wsync() {
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -198,82 +201,6 @@ __device__ inline void p3_factor16(P3Smem& sm, int base, int& fail) {
     }
 }
 
-// C = A B for 16 x 16 tiles in LDS (column-major, A(i, k) at A[k*16 + i]) on
-// one wavefront, added to acc (MFMA D layout: element r = C(4r + lane/16, lane%16)).
-__device__ inline void p3_mm16(dbl4& acc, const double* A, const double* B) {
-    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-#pragma unroll
-    for (int kk = 0; kk < 16; kk += 4)
-        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(A[(kk + lk) * 16 + li], B[li * 16 + kk + lk], acc, 0, 0, 0);
-}
-__device__ inline void p3_put16(double* C, const dbl4& acc, double scale) {
-    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) C[li * 16 + 4 * r + lk] = scale * acc[r];
-}
-
-// Epilogue: wavefront g forms the inverse X of the g-th 64 x 64 diagonal block
-// of L from the inverses Y_q of its 16 x 16 diagonal blocks (already in X64)
-// and its 16 x 16 blocks L_IJ, staged in LDS (st: 11 tiles per wavefront):
-// X_IJ = -Y_I sum_{K=J}^{I-1} L_IK X_KJ, block diagonal by block diagonal.
-__device__ inline void p3_inv64(const double* Mc, int ldi, double* X64, int m, double* stage) {
-    const int g = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    if (64 * g >= m) return;
-    const int lane = threadIdx.x & 63;
-    double* T = stage + g * 11 * 256;   // tiles: Y0..Y3, L10, L20, L21, L30, L31, L32, tmp
-    double* Xg = (double*)uniform_ptr(X64 + (int64_t)g * 4096);
-    const int Ls[6][2] = {{1, 0}, {2, 0}, {2, 1}, {3, 0}, {3, 1}, {3, 2}};
-    double v[40];
-#pragma unroll
-    for (int t = 0; t < 4; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = lane + 64 * q, i = e & 15, j = e >> 4;
-            v[4 * t + q] = ld_s(Xg, (uint32_t)((16 * t + i) + (16 * t + j) * 64));
-        }
-#pragma unroll
-    for (int t = 0; t < 6; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int e = lane + 64 * q, i = e & 15, j = e >> 4;
-            v[16 + 4 * t + q] = ld_s(Mc, (uint32_t)((64 * g + 16 * Ls[t][0] + i) + (64 * g + 16 * Ls[t][1] + j) * ldi));
-        }
-#pragma unroll
-    for (int t = 0; t < 10; ++t)
-#pragma unroll
-        for (int q = 0; q < 4; ++q) T[t * 256 + lane + 64 * q] = v[4 * t + q];
-    p3_wsync();
-    double* Y[4] = {T, T + 256, T + 512, T + 768};
-    double* L10 = T + 4 * 256; double* L20 = T + 5 * 256; double* L21 = T + 6 * 256;
-    double* L30 = T + 7 * 256; double* L31 = T + 8 * 256; double* L32 = T + 9 * 256;
-    double* tmp = T + 10 * 256;
-    // one block X_IJ = -Y_I (sum of the products given), written over slot `dst`
-    auto block = [&](int I, int J, double* dst, const double* a0, const double* b0, const double* a1, const double* b1,
-                     const double* a2, const double* b2) {
-        dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-        p3_mm16(acc, a0, b0);
-        if (a1) p3_mm16(acc, a1, b1);
-        if (a2) p3_mm16(acc, a2, b2);
-        p3_put16(tmp, acc, 1.0);
-        p3_wsync();
-        dbl4 x = {0.0, 0.0, 0.0, 0.0};
-        p3_mm16(x, Y[I], tmp);
-        p3_wsync();   // tmp read before the next block writes it
-        p3_put16(dst, x, -1.0);
-        const int li = lane & 15, lk = lane >> 4;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) st_s(Xg, (uint32_t)((16 * I + 4 * r + lk) + (16 * J + li) * 64), -x[r]);
-        p3_wsync();
-    };
-    // slots are reused once their L block is no longer needed
-    block(1, 0, L10, L10, Y[0], nullptr, nullptr, nullptr, nullptr);        // X10
-    block(2, 0, L20, L20, Y[0], L21, L10, nullptr, nullptr);                // X20 (L10 holds X10)
-    block(2, 1, L21, L21, Y[1], nullptr, nullptr, nullptr, nullptr);        // X21
-    block(3, 0, L30, L30, Y[0], L31, L10, L32, L20);                        // X30 (L20 holds X20)
-    block(3, 1, L31, L31, Y[1], L32, L21, nullptr, nullptr);                // X31 (L21 holds X21)
-    block(3, 2, L32, L32, Y[2], nullptr, nullptr, nullptr, nullptr);        // X32
-}
-
 // Slots of the 16 x 16 tiles of L in the LDS pool, for np = 4, 8, 12, 16 row
 // tiles.  Tile (I, k), I > k, enters the pool as a reduced tile of panel k
 // during U(k-1) (the prologue for k = 0), is solved in place at S(k), and is
@@ -327,7 +254,8 @@ __device__ inline int p3_slot(uint32_t tab, int I, int k) {
 // whatever its indices give, and neither stores anything.
 
 // S(p): L_Ip^T = Y C_Ip^T for the tiles I > p, in place in the pool (each
-// tile read whole before it is written) and to global memory.
+// tile read whole before it is written) and to global memory (device-coherent
+// stores: a concurrent kernel reads them).
 template <int S0>
 __device__ __forceinline__ void p3_solve_slots(P3Smem& sm, double* Mw, int ldi, uint32_t tab, int w, int np, int p,
                                                int lane, int li, int lk) {
@@ -353,7 +281,7 @@ __device__ __forceinline__ void p3_solve_slots(P3Smem& sm, double* Mw, int ldi, 
         if (I > p && I < np) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                st_s(Mw, (uint32_t)((16 * I + li) + (c0 + 4 * r + lk) * ldi), o[q][r]);
+                st_coh_s(Mw, (uint32_t)((16 * I + li) + (c0 + 4 * r + lk) * ldi), o[q][r]);
                 X[q][(4 * r + lk) * 16 + li] = o[q][r];
             }
         }
@@ -453,10 +381,17 @@ __device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& s
 // dimension ld), m a multiple of 64, m <= 256; zeros go only into the upper
 // parts of the diagonal 16 x 16 blocks (the rest of the strict upper triangle
 // is left as it is, for the caller to clear off the dependency chain).
-// X64 + q*4096: inverse of the q-th 64 x 64 diagonal block of L
-// (column-major, entries above its 16 x 16 block diagonal not written).
-// Thread 0 returns the first failing local column (or -1) and the log det
-// pair.
+// Yd + 256 p: Y_p = L_pp^{-1}, the inverse of the p-th 16 x 16 diagonal block
+// (column-major, upper part 0).  Thread 0 returns the first failing local
+// column (or -1) and the log det pair.
+//
+// Panels are announced as they are finished: *fpo is raised by one for each
+// (agent-scope relaxed atomic add), once the off-diagonal tiles L_Ip (I > p)
+// and Y_p are in global memory, written with device-coherent stores, so a
+// kernel running concurrently on other compute units may read them with
+// device-coherent loads as soon as it sees *fpo > p.  (Panel p is announced
+// at the end of U(p), when its stores have long completed; the last one at
+// the end.)
 //
 // Software pipeline over the 16-column panels p, two phases per panel:
 //   S(p): L_pp and Y_pp go out; wavefronts 1..3 solve their tiles of panel p
@@ -470,8 +405,8 @@ __device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& s
 // Every tile of L stays in the LDS pool from its reduction to its last use,
 // so global memory is read only for the raw tiles, each once.  The chain of
 // diagonal factorizations overlaps all the other work.
-__device__ inline void potrf3(double* M, int64_t ld, int m, double* X64, P3Smem& sm, int* fail_out, double* ls_out,
-                              double* lc_out) {
+__device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& sm, int* fail_out, double* ls_out,
+                              double* lc_out, int* fpo) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int np = m / 16;
@@ -520,8 +455,7 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* X64, P3Smem&
         const int c0 = 16 * p;
         // ---- S(p)
         if (w == 0) {
-            double* Xg = (double*)uniform_ptr(X64 + (int64_t)(p >> 2) * 4096);
-            const int xo = 16 * (p & 3);
+            double* Yg = (double*)uniform_ptr(Yd + (int64_t)p * 256);
             double dv[4], yv[4];
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -533,7 +467,7 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* X64, P3Smem&
             for (int q = 0; q < 4; ++q) {
                 const int i = lane & 15, j = (lane >> 4) + 4 * q;
                 st_s(Mw, (uint32_t)((c0 + i) + (c0 + j) * ldi), dv[q]);
-                st_s(Xg, (uint32_t)((xo + i) + (xo + j) * 64), yv[q]);
+                st_coh_s(Yg, (uint32_t)(i + 16 * j), yv[q]);
             }
         } else {
             // slots s >= s1 hold the tiles I > p
@@ -575,16 +509,17 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* X64, P3Smem&
                 default: p3_update_slots<4>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
             }
         }
-        // D, Y of p+1; panel p+1 in the pool; Dn.  The global stores of L
-        // stay in flight: nothing in the loop reads them back.
-        p3_bar_lds();
+        // D, Y of p+1; panel p+1 in the pool; Dn; and the stores of panel p
+        // complete, so it is announced.
+        p3_bar_all();
+        if (threadIdx.x == 0) __hip_atomic_fetch_add(fpo, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
-    __syncthreads();
-    // log det: 2 log L_jj in parallel; the 64-block inverses; then a
-    // fixed-order compensated sum (lane l of wavefront 0 sums entries l, l+64,
-    // ..., then the lanes are joined pairwise by a butterfly)
+    p3_bar_all();   // the last panel's stores complete
+    if (threadIdx.x == 0) __hip_atomic_fetch_add(fpo, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // log det: 2 log L_jj in parallel, then a fixed-order compensated sum
+    // (lane l of wavefront 0 sums entries l, l+64, ..., then the lanes are
+    // joined pairwise by a butterfly)
     for (int t = threadIdx.x; t < m; t += 256) sm.dg[t] = 2.0 * log(sm.dg[t]);
-    p3_inv64(Mc, ldi, X64, m, &sm.pool[0][0]);
     __syncthreads();
     if (w == 0) {
         double ps = 0.0, pc = 0.0;

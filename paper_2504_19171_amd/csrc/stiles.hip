@@ -60,6 +60,9 @@ static Lay to_dev(const stiles_layout& s) {
 // ---------------------------------------------------------------------------
 // Small kernels
 // ---------------------------------------------------------------------------
+__global__ void k_zero_ints(int* p, int64_t n) {
+    for (int64_t i = threadIdx.x + (int64_t)blockIdx.x * blockDim.x; i < n; i += (int64_t)blockDim.x * gridDim.x) p[i] = 0;
+}
 __global__ void k_set_int(int* p, int v) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
 }
@@ -164,41 +167,9 @@ __global__ __launch_bounds__(NT) void k_trsm_generic(double* C, int64_t ld, int 
 // Factor kernels of the band tile columns
 // ---------------------------------------------------------------------------
 
-// POTRF of one diagonal tile (m = b) plus the inverses of its 64 x 64
-// diagonal blocks (for the panel TRSM): X64 + q*4096, 64 x 64 column-major.
-__global__ __launch_bounds__(NT) void k_potrf_x64(double* M, int64_t ld, int m, double* X64, double* ldp, int* info,
-                                                 int64_t col_base) {
-    extern __shared__ double smem[];
-    int fail;
-    double s, c;
-    potrf_tile(M, ld, m, smem, &fail, &s, &c);
-    if (threadIdx.x == 0) {
-        ldp[0] = s;
-        ldp[1] = c;
-        if (fail >= 0) atomicMin(info, (int)(col_base + fail + 1));
-    }
-    __syncthreads();
-    inv64_blocks(M, ld, X64, m, smem);
-}
-
-// POTRF of one diagonal tile with the register-resident left-looking kernel
-// (potrf3.hpp), plus the 64 x 64 diagonal-block inverses of L.
-__global__ __launch_bounds__(NT) void k_potrf3(double* M, int64_t ld, int m, double* X64, double* ldp, int* info,
-                                              int64_t col_base) {
-    __shared__ P3Smem sm;
-    int fail;
-    double s, c;
-    potrf3(M, ld, m, X64, sm, &fail, &s, &c);
-    if (threadIdx.x == 0) {
-        ldp[0] = s;
-        ldp[1] = c;
-        if (fail >= 0) atomicMin(info, (int)(col_base + fail + 1));
-    }
-}
-
 // Strict upper triangles of the band diagonal tiles set to 0 (the layout's
-// convention for L; k_potrf3 leaves them, as nothing in the factorization
-// reads them).  Eight workgroups per tile, b/8 columns each.
+// convention for L; the diagonal-tile POTRF leaves them, as nothing in the
+// factorization reads them).  Eight workgroups per tile, b/8 columns each.
 __global__ __launch_bounds__(NT) void k_zero_upper(double* Lm, Lay L) {
     const int64_t J = blockIdx.x >> 3;
     const int cw = L.b / 8, c0 = (int)(blockIdx.x & 7) * cw;
@@ -207,171 +178,323 @@ __global__ __launch_bounds__(NT) void k_zero_upper(double* Lm, Lay L) {
         for (int i = threadIdx.x; i < c; i += NT) T[i + (int64_t)c * L.b] = 0.0;
 }
 
-// Panel TRSM, one 16-row block per workgroup: R = C L_JJ^{-T} in place, by
-// forward substitution over the 64-column blocks q of the tile,
-//   Z_q = C_q - sum_{q' < q} R_q' L_{q,q'}^T,   R_q = Z_q X64_q^T,
-// with the transposed products formed on the matrix cores (Z^T = C^T - L R^T,
-// R^T = X64 Z^T) so that every global access runs down a column.  Row block
-// g0 + blockIdx.x of the rows below tile J: band tiles J+1..J+s (b/16 blocks
-// each), then the arrow tile (a_p/16 blocks).  Wavefront w owns columns
-// 64q + 16w .. 64q + 16w + 15 of each step.
+// Panel TRSM of one 16-row block C (16 x b, leading dimension ld), R = C
+// L_JJ^{-T} in place, one 16-column panel p per step:
+//   Z_p = C_p - sum_{p' < p} R_p' L_{p,p'}^T,   R_p = Z_p Y_p^T   (Y_p = L_pp^{-1}),
+// with the transposed products on the matrix cores (Z_p^T = C_p^T - L_{p,p'}
+// R_p'^T, R_p^T = Y_p Z_p^T) so every global access runs down a column.  The
+// reduction of a step is spread over the 4 wavefronts (panels p' = w, w+4,
+// ... of wavefront w) and summed in LDS in a fixed order; the tiles L_{p,p'}
+// of the next step are loaded while the current one is multiplied.  R stays in
+// LDS ([column][row]) and is zero where not yet computed, so a product with a
+// panel that is not there yet adds nothing and the loop has no branches.
+//
+// Concurrent mode (fpo != nullptr): L_JJ is being factored by k_potrf3 at the
+// same time; step p waits until *fpo > p, reads L and Y with device-coherent
+// loads, writes R with device-coherent stores and raises *ftr after each step.
 #define TR_LD 16
-#define TR_MAXA 48   // A operands of one step per lane: (b/64 - 1) * 16 for b = 256
-__device__ inline void tr_bar_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
-__global__ __launch_bounds__(NT) void k_trsm16(double* Lm, Lay L, int64_t J, const double* X64, int g0) {
-    __shared__ double sR[256 * TR_LD];   // R, [column][row]
-    __shared__ double sZ[64 * TR_LD];    // Z of the current step, [column][row]
-    const int g = g0 + blockIdx.x;
-    const int nbr = L.b / 16, s = L.s(J);
-    double* C;
-    int ld;
-    if (g < s * nbr) { C = Lm + L.band(J, 1 + g / nbr) + (g % nbr) * 16; ld = L.b; }
-    else { C = Lm + L.arrow(J) + (g - s * nbr) * 16; ld = L.ap; }
-    C = (double*)uniform_ptr(C);
-    const double* Ljj = uniform_ptr(Lm + L.band(J, 0));
-    const double* Xb = uniform_ptr(X64);
+struct TrSmem {
+    double R[256 * TR_LD];
+    double P[4][256];
+    int sh;
+};
+__device__ inline bool tr_panel(double* C, int ld, const double* Ljj, const double* Yd, int b, const int* fpo,
+                                int* ftr, const Sched& sc, TrSmem& sm) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-    const int b = L.b;
-    const int nq = b / 64;
-    const int KX = 16 * (w + 1);
-    // operands of step 0 (C tile and X64 rows; no A operands yet)
+    const int np = b / 16;
+    const bool coh = fpo != nullptr;
+    C = (double*)uniform_ptr(C);
+    Ljj = uniform_ptr(Ljj);
+    Yd = uniform_ptr(Yd);
+    for (int e = threadIdx.x; e < b * TR_LD; e += NT) sm.R[e] = 0.0;
+    auto ldL = [&](uint32_t idx) { return coh ? ld_coh_s(Ljj, idx) : ld_s(Ljj, idx); };
+    // A operands of step s for this wavefront: -L_{s,p'} for p' = w + 4t (the
+    // tile column clamped into the finished part; its product is then with a
+    // zero panel of R)
+    auto fetchA = [&](double (&a)[4][4], int s) {
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int pa = imax_(0, imin_(w + 4 * t, s - 1));
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) a[t][kk] = -ldL((uint32_t)((16 * s + li) + (16 * pa + 4 * kk + lk) * b));
+        }
+    };
+    double acur[4][4], anext[4][4];
     dbl4 cn;
-    double xn[16];
 #pragma unroll
-    for (int r = 0; r < 4; ++r) cn[r] = ld_s(C, (uint32_t)(li + (16 * w + 4 * r + lk) * ld));
+    for (int r = 0; r < 4; ++r) cn[r] = ld_s(C, (uint32_t)(li + (4 * r + lk) * ld));
 #pragma unroll
-    for (int t = 0; t < 16; ++t) xn[t] = ld_s(Xb, (uint32_t)((16 * w + li) + (4 * t + lk) * 64));
-    for (int q = 0; q < nq; ++q) {
-        const int c0 = 64 * q + 16 * w;
-        const int K = 64 * q;
-        // Z^T tile (columns c0.., all 16 rows): element r = Z^T[4r + lk][li] = Z[li][c0 + 4r + lk]
-        dbl4 a0 = cn, a1 = {0.0, 0.0, 0.0, 0.0};
-        double xv[16];
+    for (int t = 0; t < 4; ++t)
 #pragma unroll
-        for (int t = 0; t < 16; ++t) xv[t] = xn[t];
-        double av[TR_MAXA];
-#pragma unroll
-        for (int t = 0; t < TR_MAXA; ++t)
-            av[t] = -ld_s(Ljj, (uint32_t)((c0 + li) + imin_(4 * t + lk, b - 1) * b));
-        // next step's C tile and X64 rows go out now
-        if (q + 1 < nq) {
-            const int c1 = c0 + 64;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) cn[r] = ld_s(C, (uint32_t)(li + (c1 + 4 * r + lk) * ld));
-#pragma unroll
-            for (int t = 0; t < 16; ++t) xn[t] = ld_s(Xb, (uint32_t)((q + 1) * 4096 + (16 * w + li) + (4 * t + lk) * 64));
-        }
-#pragma unroll
-        for (int t = 0; t < TR_MAXA; t += 2) {
-            if (4 * t < K) {
-                a0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t], sR[(4 * t + lk) * TR_LD + li], a0, 0, 0, 0);
-                a1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av[t + 1], sR[(4 * t + 4 + lk) * TR_LD + li], a1, 0, 0, 0);
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sZ[(16 * w + 4 * r + lk) * TR_LD + li] = a0[r] + a1[r];
-        tr_bar_lds();
-        // R^T rows 16w.. of block q = X64_q(rows 16w..) Z^T; X64 is lower triangular
-        dbl4 o0 = {0.0, 0.0, 0.0, 0.0}, o1 = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int t = 0; t < 16; t += 2) {
-            if (4 * t < KX) {
-                o0 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[t], sZ[(4 * t + lk) * TR_LD + li], o0, 0, 0, 0);
-                o1 = __builtin_amdgcn_mfma_f64_16x16x4f64(xv[t + 1], sZ[(4 * t + 4 + lk) * TR_LD + li], o1, 0, 0, 0);
-            }
-        }
+        for (int kk = 0; kk < 4; ++kk) acur[t][kk] = 0.0;
+    __syncthreads();
+    for (int p = 0; p < np; ++p) {
+        if (coh && !sched_wait(sc, (int*)fpo, p + 1, &sm.sh)) return false;
+        // loads for this step's Y and the next step's operands (panels <= p
+        // are finished, so the tiles L_{p+1,p'}, p' <= p, are there)
+        double yv[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
-            const double v = o0[r] + o1[r];
-            sR[(c0 + 4 * r + lk) * TR_LD + li] = v;
-            st_s(C, (uint32_t)(li + (c0 + 4 * r + lk) * ld), v);
+            const uint32_t yi = (uint32_t)(p * 256 + li + 16 * (4 * r + lk));
+            yv[r] = coh ? ld_coh_s(Yd, yi) : ld_s(Yd, yi);
         }
-        tr_bar_lds();   // sR and sZ reuse; the stores to C are read by no one here
+        const int pn = imin_(p + 1, np - 1);
+        fetchA(anext, pn);
+        dbl4 cnext;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) cnext[r] = ld_s(C, (uint32_t)(li + (16 * pn + 4 * r + lk) * ld));
+        // this wavefront's part of Z_p^T
+        dbl4 z;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z[r] = (w == 0) ? cn[r] : 0.0;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int p2 = imin_(w + 4 * t, np - 1);
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk)
+                z = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[t][kk], sm.R[(16 * p2 + 4 * kk + lk) * TR_LD + li], z, 0,
+                                                         0, 0);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) sm.P[w][r * 64 + lane] = z[r];
+        __syncthreads();
+        if (w == 0) {
+            // Z_p^T in the D layout is the B operand of R_p^T = Y_p Z_p^T as it stands
+            dbl4 zs, o = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                zs[r] = ((sm.P[0][r * 64 + lane] + sm.P[1][r * 64 + lane]) + sm.P[2][r * 64 + lane]) +
+                        sm.P[3][r * 64 + lane];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) o = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[r], zs[r], o, 0, 0, 0);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                sm.R[(16 * p + 4 * r + lk) * TR_LD + li] = o[r];
+                const uint32_t ci = (uint32_t)(li + (16 * p + 4 * r + lk) * ld);
+                if (coh) st_coh_s(C, ci, o[r]);
+                else st_s(C, ci, o[r]);
+            }
+        }
+        if (ftr) sched_signal(sc, ftr, 0);   // waits for the stores, then a barrier
+        else __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 4; ++t)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) acur[t][kk] = anext[t][kk];
+        cn = cnext;
     }
+    return true;
 }
 
-// Trailing update after tile column J on 32 x 32 blocks (reduction over the
-// b columns of tile J spread over 4 wavefronts):
+// ---------------------------------------------------------------------------
+// The factorization of one tile column J as one persistent launch: POTRF of
+// the diagonal tile, the panel TRSM of every 16-row block below it and the
+// trailing update of every 64 x 64 target block, run concurrently and
+// pipelined on the 16-column panels of L_JJ through device counters.
+// ---------------------------------------------------------------------------
+
+// Per tile column counters (ints, zeroed once per factorization): the ticket
+// counter, the number of panels of L_JJ announced by POTRF, then per 16-row
+// block of the TRSM the number of its finished steps.
+#define CF_TICKET 0
+#define CF_PO 1
+#define CF_TR 4
+__host__ __device__ inline int col_tr_blocks(const Lay& L, int64_t J) { return L.s(J) * (L.b / 16) + L.ap / 16; }
+__host__ __device__ inline int col_stride(const Lay& L) { return CF_TR + L.bt * (L.b / 16) + L.ap / 16; }
+
+// Trailing-update target blocks of tile column J, 64 x 64, in this order:
 //   band (J+d, J+e), 1 <= e <= d <= s:  -= L_{J+d,J} L_{J+e,J}^T   (lower blocks when d == e)
 //   arrow (A, J+e):                      -= L_{A,J} L_{J+e,J}^T
 //   corner (lower blocks):               -= L_{A,J} L_{A,J}^T
-__host__ __device__ inline int upd32_count(const Lay& L, int64_t J) {
-    const int C32 = L.b / 32, s = L.s(J), na = (L.ap + 31) / 32;
+// (the block of (J+1, J+1) that the next POTRF needs first comes first).
+struct UpBlock {
+    const double* A;   // operand rows (64-row block), leading dimension lda, rows_a valid in its tile
+    const double* B;
+    double* O;         // target block, leading dimension ldo
+    int lda, ldb, ldo;
+    int rows_a, rows_b;   // valid rows from the block's first row on (<= 64)
+    int ga, gb;           // TRSM row blocks (16 rows) of the first rows of A and B
+    int diag;             // a diagonal block of a symmetric target: lower part only
+};
+__host__ __device__ inline int col_up_blocks(const Lay& L, int64_t J) {
+    const int C64 = L.b / 64, s = L.s(J), na = (L.ap + 63) / 64;
     int cnt = 0;
     for (int d = 1; d <= s; ++d)
-        for (int e = 1; e <= d; ++e) cnt += (d == e) ? C32 * (C32 + 1) / 2 : C32 * C32;
-    if (L.ap > 0) cnt += s * na * C32 + na * (na + 1) / 2;
+        for (int e = 1; e <= d; ++e) cnt += (d == e) ? C64 * (C64 + 1) / 2 : C64 * C64;
+    if (L.ap > 0) cnt += s * na * C64 + na * (na + 1) / 2;
     return cnt;
 }
-
-__global__ __launch_bounds__(NT) void k_update32(double* Lm, Lay L, int64_t J, int t0) {
-    __shared__ double smem[WS_SMEM_DOUBLES + 32 * WR_LD];
-    double* red = smem + WS_SMEM_DOUBLES;
-    const int C32 = L.b / 32, s = L.s(J), na = (L.ap + 31) / 32;
-    int t = t0 + blockIdx.x;
-    const double *Ap = nullptr, *Bp = nullptr;
-    int64_t lda = L.b, ldb = L.b, ldo = L.b;
-    int va = 32, vb = 32;
-    double* O = nullptr;
-    bool found = false;
-    for (int d = 1; d <= s && !found; ++d) {
-        for (int e = 1; e <= d && !found; ++e) {
-            const int cnt = (d == e) ? C32 * (C32 + 1) / 2 : C32 * C32;
+__device__ inline UpBlock col_up_decode(double* Lm, const Lay& L, int64_t J, int t) {
+    const int C64 = L.b / 64, s = L.s(J), na = (L.ap + 63) / 64, nbr = L.b / 16, b = L.b;
+    UpBlock u;
+    for (int d = 1; d <= s; ++d) {
+        for (int e = 1; e <= d; ++e) {
+            const int cnt = (d == e) ? C64 * (C64 + 1) / 2 : C64 * C64;
             if (t < cnt) {
-                int rb, cb;
-                if (d == e) tri_decode(t, rb, cb);
-                else { rb = t % C32; cb = t / C32; }
-                Ap = Lm + L.band(J, d) + rb * 32;
-                Bp = Lm + L.band(J, e) + cb * 32;
-                O = Lm + L.band(J + e, d - e) + rb * 32 + (int64_t)cb * 32 * L.b;
-                found = true;
-            } else {
-                t -= cnt;
+                int i, j;
+                if (d == e) tri_decode(t, i, j);
+                else { i = t % C64; j = t / C64; }
+                u.A = Lm + L.band(J, d) + 64 * i; u.lda = b; u.rows_a = 64; u.ga = (d - 1) * nbr + 4 * i;
+                u.B = Lm + L.band(J, e) + 64 * j; u.ldb = b; u.rows_b = 64; u.gb = (e - 1) * nbr + 4 * j;
+                u.O = Lm + L.band(J + e, d - e) + 64 * i + (int64_t)64 * j * b; u.ldo = b;
+                u.diag = (d == e && i == j);
+                return u;
             }
+            t -= cnt;
         }
     }
-    if (!found && L.ap > 0) {
-        for (int e = 1; e <= s && !found; ++e) {
-            const int cnt = na * C32;
-            if (t < cnt) {
-                const int rb = t % na, cb = t / na;
-                Ap = Lm + L.arrow(J) + rb * 32; lda = L.ap; va = imin_(32, L.ap - rb * 32);
-                Bp = Lm + L.band(J, e) + cb * 32;
-                O = Lm + L.arrow(J + e) + rb * 32 + (int64_t)cb * 32 * L.ap; ldo = L.ap;
-                found = true;
-            } else {
-                t -= cnt;
+    const int ga0 = s * nbr;
+    if (t < s * na * C64) {
+        const int e = 1 + t / (na * C64), r = t % (na * C64), i = r % na, j = r / na;
+        u.A = Lm + L.arrow(J) + 64 * i; u.lda = L.ap; u.rows_a = imin_(64, L.ap - 64 * i); u.ga = ga0 + 4 * i;
+        u.B = Lm + L.band(J, e) + 64 * j; u.ldb = b; u.rows_b = 64; u.gb = (e - 1) * nbr + 4 * j;
+        u.O = Lm + L.arrow(J + e) + 64 * i + (int64_t)64 * j * L.ap; u.ldo = L.ap;
+        u.diag = 0;
+        return u;
+    }
+    t -= s * na * C64;
+    int i, j;
+    tri_decode(t, i, j);
+    u.A = Lm + L.arrow(J) + 64 * i; u.lda = L.ap; u.rows_a = imin_(64, L.ap - 64 * i); u.ga = ga0 + 4 * i;
+    u.B = Lm + L.arrow(J) + 64 * j; u.ldb = L.ap; u.rows_b = imin_(64, L.ap - 64 * j); u.gb = ga0 + 4 * j;
+    u.O = Lm + L.corner() + 64 * i + (int64_t)64 * j * L.ap; u.ldo = L.ap;
+    u.diag = (i == j);
+    return u;
+}
+
+// Thread 0 waits until every flag[k], k < n, is at least target; then the
+// workgroup goes on (false: stop, the kernel is being abandoned).
+__device__ inline bool col_wait(const Sched& sc, const int* flag, int n, int target, int* sh) {
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        const int64_t t0 = wall_clock64();
+        for (int k = 0; k < n && ok; ++k) {
+            while (__hip_atomic_load(flag + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+                if (__hip_atomic_load(sc.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+                if (wall_clock64() - t0 > sc.spin_limit) {
+                    int zero = 0;
+                    __hip_atomic_compare_exchange_strong(sc.err, &zero, STILES_ETIMEOUT, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
             }
         }
-        if (!found) {
-            int rb, cb;
-            tri_decode(t, rb, cb);
-            Ap = Lm + L.arrow(J) + rb * 32; lda = L.ap; va = imin_(32, L.ap - rb * 32);
-            Bp = Lm + L.arrow(J) + cb * 32; ldb = L.ap; vb = imin_(32, L.ap - cb * 32);
-            O = Lm + L.corner() + rb * 32 + (int64_t)cb * 32 * L.ap; ldo = L.ap;
-        }
+        *sh = ok;
+    }
+    __syncthreads();
+    const bool ok = __builtin_amdgcn_readfirstlane(*sh) != 0;
+    __syncthreads();
+    return ok;
+}
+
+// One 64 x 64 target block, accumulated one 16-column panel of tile column J
+// at a time as the TRSM steps of its rows are announced.  Wavefront w owns
+// the 32 x 32 quarter (w/2, w%2), four 16 x 16 tiles; tiles past the valid
+// rows, and tiles above the diagonal of a diagonal block, are not stored.
+__device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, const Sched& sc, int* sh) {
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
+    const int qi = w >> 1, qj = w & 1;
+    const double* A = uniform_ptr(u.A);
+    const double* B = uniform_ptr(u.B);
+    double* O = (double*)uniform_ptr(u.O);
+    const int ta = (u.rows_a + 15) / 16, tb = (u.rows_b + 15) / 16;   // valid 16-row tiles
+    int ra[2], rb[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) {
+        ra[x] = imin_(2 * qi + x, ta - 1);
+        rb[x] = imin_(2 * qj + x, tb - 1);
     }
     dbl4 acc[2][2];
+    double ov[2][2][4];
 #pragma unroll
-    for (int i = 0; i < 2; ++i)
+    for (int x = 0; x < 2; ++x)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-    // the output block is read now, so its round trip overlaps the products
-    double ov[4];
+        for (int y = 0; y < 2; ++y) {
+            acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + 256 * q, i = e & 31, j = e >> 5;
-        ov[q] = (i < va && j < vb) ? O[i + (int64_t)j * ldo] : 0.0;
+            for (int r = 0; r < 4; ++r)
+                ov[x][y][r] = ld_s(O, (uint32_t)((16 * ra[x] + li) + (16 * rb[y] + 4 * r + lk) * u.ldo));
+        }
+    for (int p = 0; p < np; ++p) {
+        if (!col_wait(sc, ftr + u.ga, ta, p + 1, sh)) return false;
+        if (!col_wait(sc, ftr + u.gb, tb, p + 1, sh)) return false;
+        double av[2][4], bv[2][4];
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                av[x][kk] = ld_coh_s(A, (uint32_t)((16 * ra[x] + li) + (16 * p + 4 * kk + lk) * u.lda));
+                bv[x][kk] = ld_coh_s(B, (uint32_t)((16 * rb[x] + li) + (16 * p + 4 * kk + lk) * u.ldb));
+            }
+        // element r of acc[x][y]: sum_k A[16 ra + li][k] B[16 rb + 4r + lk][k]
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+            for (int x = 0; x < 2; ++x)
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[y][kk], av[x][kk], acc[x][y], 0, 0, 0);
     }
-    // B(k, j) = L_cols[j][k]: the transposed access of the column rows
-    const Seg sg = mkseg(Ap, lda, 0, Bp, ldb, 1, L.b, va);
-    wave_segs(acc, 1, L.b, smem, [&](int) { return sg; });
-    wave_reduce(acc, smem, red);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + 256 * q, i = e & 31, j = e >> 5;
-        if (i < va && j < vb) O[i + (int64_t)j * ldo] = ov[q] - red[j * WR_LD + i];
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y) {
+            const int ti = 2 * qi + x, tj = 2 * qj + y;
+            if (ti < ta && tj < tb && !(u.diag && ti < tj)) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    st_s(O, (uint32_t)((16 * ti + li) + (16 * tj + 4 * r + lk) * u.ldo), ov[x][y][r] - acc[x][y][r]);
+            }
+        }
+    return true;
+}
+
+// Tickets, in an order where every task waits only for smaller ones (so the
+// launch cannot deadlock, however many workgroups are resident): 0 is the
+// POTRF of L_JJ, then the TRSM row blocks (tile J+1 first), then the update
+// blocks.  The factorization of the next tile column is the next launch.
+union ColSmem {
+    P3Smem po;
+    TrSmem tr;
+};
+__global__ __launch_bounds__(NT) void k_column(double* Lm, Lay L, int64_t J, double* Yd, int* cf, Sched sc,
+                                               double* ldp, int* info) {
+    __shared__ ColSmem sm;
+    __shared__ int sh;
+    const int ntr = col_tr_blocks(L, J);
+    const int ntasks = 1 + ntr + col_up_blocks(L, J);
+    const int nbr = L.b / 16, s = L.s(J);
+    int* fpo = cf + CF_PO;
+    int* ftr = cf + CF_TR;
+    Sched st = sc;
+    st.ticket = cf + CF_TICKET;
+    for (;;) {
+        const int t = sched_next(st, ntasks, &sh);
+        if (t < 0) return;
+        if (t == 0) {
+            int fail;
+            double ls, lc;
+            potrf3(Lm + L.band(J, 0), L.b, L.b, Yd, sm.po, &fail, &ls, &lc, fpo);
+            if (threadIdx.x == 0) {
+                ldp[0] = ls;
+                ldp[1] = lc;
+                if (fail >= 0) atomicMin(info, (int)(J * L.b + fail + 1));
+            }
+        } else if (t <= ntr) {
+            const int g = t - 1;
+            double* C;
+            int ld;
+            if (g < s * nbr) { C = Lm + L.band(J, 1 + g / nbr) + (g % nbr) * 16; ld = L.b; }
+            else { C = Lm + L.arrow(J) + (g - s * nbr) * 16; ld = L.ap; }
+            if (!tr_panel(C, ld, Lm + L.band(J, 0), Yd, L.b, fpo, ftr + g, st, sm.tr)) return;
+        } else {
+            const UpBlock u = col_up_decode(Lm, L, J, t - 1 - ntr);
+            if (!col_update(u, ftr, L.b / 16, st, &sh)) return;
+        }
     }
 }
 
@@ -395,7 +518,7 @@ __global__ void k_zero_block(double* C, int64_t ld, int rows, int cols) {
 }
 
 // Final log det (Neumaier sum of the per-block partials, in order) and info.
-__global__ void k_factor_final(const double* ldp, int nparts, const int* info_ws, double* logdet,
+__global__ void k_factor_final(const double* ldp, int nparts, const int* info_ws, const int* err, double* logdet,
                                int* info) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double s = 0.0, c = 0.0;
@@ -403,7 +526,7 @@ __global__ void k_factor_final(const double* ldp, int nparts, const int* info_ws
         neumaier(s, c, ldp[2 * i]);
         neumaier(s, c, ldp[2 * i + 1]);
     }
-    const int f = *info_ws;
+    const int f = (*err != 0) ? *err : *info_ws;
     *info = (f == 0x7fffffff) ? 0 : f;
     *logdet = (f == 0x7fffffff) ? (s + c) : __builtin_nan("");
 }
@@ -897,13 +1020,6 @@ static int64_t spin_limit_ticks(const DevInfo& di) {
     return (int64_t)(ms * (double)di.clock_khz);
 }
 
-// STILES_POTRF=1 selects the 16-panel right-looking diagonal-tile kernel
-// instead of the default left-looking one (for comparisons).
-static int g_potrf_kind = [] {
-    const char* e = getenv("STILES_POTRF");
-    return e ? atoi(e) : 0;
-}();
-
 static int debug_withhold() {
     if (const char* e = getenv("STILES_DEBUG_WITHHOLD")) return atoi(e);
     return -1;
@@ -922,44 +1038,6 @@ static int grid_for(int64_t work) {
 // stream rather than the caller's keeps the overlap when the caller uses the
 // legacy default stream.  The mutex serialises the enqueue of concurrent
 // factor calls on one device (their kernels may still overlap).
-struct Side {
-    hipStream_t a = nullptr, b = nullptr;
-    hipEvent_t fork = nullptr, po = nullptr, tr = nullptr, up = nullptr, ja = nullptr, jb = nullptr;
-    std::mutex mu;
-};
-static Side g_side[64];
-
-static int side_get(Side** out) {
-    int d = 0;
-    if (hipGetDevice(&d) != hipSuccess || d < 0 || d >= 64) return STILES_EHIP;
-    Side& sd = g_side[d];
-    std::lock_guard<std::mutex> g(g_dmu);
-    if (!sd.b) {
-        hipStream_t a, b;
-        if (hipStreamCreateWithFlags(&a, hipStreamNonBlocking) != hipSuccess) return STILES_EHIP;
-        // STILES_RESERVE_CUS=r keeps the off-chain stream off the first r
-        // compute units, so the chain never waits for a free unit.
-        int reserve = 0;
-        if (const char* e = getenv("STILES_RESERVE_CUS")) reserve = atoi(e);
-        int cus = 0;
-        if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, d) != hipSuccess) return STILES_EHIP;
-        if (reserve > 0 && reserve < cus) {
-            std::vector<uint32_t> mask((cus + 31) / 32, 0u);
-            for (int c = reserve; c < cus; ++c) mask[c / 32] |= 1u << (c % 32);
-            if (hipExtStreamCreateWithCUMask(&b, (uint32_t)mask.size(), mask.data()) != hipSuccess) return STILES_EHIP;
-        } else if (hipStreamCreateWithFlags(&b, hipStreamNonBlocking) != hipSuccess) {
-            return STILES_EHIP;
-        }
-        hipEvent_t* ev[6] = {&sd.fork, &sd.po, &sd.tr, &sd.up, &sd.ja, &sd.jb};
-        for (auto e : ev)
-            if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess) return STILES_EHIP;
-        sd.a = a;
-        sd.b = b;
-    }
-    *out = &sd;
-    return 0;
-}
-
 extern "C" {
 
 #ifdef STILES_TASK_TRACE
@@ -1032,10 +1110,13 @@ int stiles_layout_init(int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile
 
 size_t stiles_factor_workspace_bytes(const stiles_layout* lay) {
     if (!lay) return 0;
-    // head + log det partials (N + 2 blocks) + the 256 x 256 inverse of the
-    // blocked corner + the 64 x 64 diagonal-block inverses of every L_JJ.
+    // head (info, error words) + log det partials (N + 2 blocks) + the
+    // 256 x 256 inverse of the blocked corner + the 16 x 16 diagonal-block
+    // inverses of every L_JJ + the per tile column counters.
+    const Lay L = to_dev(*lay);
     return WS_HEAD + sizeof(double) * (size_t)(2 * (lay->nt + 2)) +
-           sizeof(double) * (size_t)(256 * 256 + lay->nt * (int64_t)(lay->tile / 64) * 4096);
+           sizeof(double) * (size_t)(256 * 256 + lay->nt * (int64_t)lay->tile * 16) +
+           sizeof(int) * (size_t)(lay->nt * (int64_t)col_stride(L));
 }
 
 // selinv workspace: head (info, ticket, error words), the Phase 1 tiles
@@ -1079,12 +1160,17 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     int* winfo = (int*)ws;
     double* ldp = (double*)(ws + WS_HEAD);
     double* Xc = ldp + 2 * (L.nt + 2);
-    double* X64 = Xc + 256 * 256;
-    const int64_t x64_per = (int64_t)(L.b / 64) * 4096;
-    Side* sd;
-    if (side_get(&sd)) return STILES_EHIP;
-    std::lock_guard<std::mutex> lk(sd->mu);
-    hipStream_t sa = sd->a, sb = sd->b;
+    double* Yd = Xc + 256 * 256;
+    const int64_t y_per = (int64_t)L.b * 16;
+    int* cf = (int*)(Yd + L.nt * y_per);
+    const int cstride = col_stride(L);
+    DevInfo di;
+    if (dev_info(&di)) return STILES_EHIP;
+    Sched sc;
+    sc.ticket = nullptr;
+    sc.err = winfo + 16;
+    sc.spin_limit = spin_limit_ticks(di);
+    sc.withhold = -1;
 
     if (A != Lm) {
         hipEvent_t tm = tm_begin(st);
@@ -1092,51 +1178,18 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
         tm_end(tm, STILES_TK_OTHER, st);
     }
     LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, winfo, 0x7fffffff);
-    // Two streams.  Stream a carries the dependency chain of the diagonal
-    // tiles: POTRF(J) -> TRSM of tile (J+1, J) -> its SYRK into (J+1, J+1)
-    // -> POTRF(J+1).  Stream b carries the rest of column J (TRSM of the
-    // other rows, the other trailing updates), which overlaps the next steps
-    // of the chain.
-    HIPCHK(hipEventRecord(sd->fork, st));
-    HIPCHK(hipStreamWaitEvent(sa, sd->fork, 0));
-    HIPCHK(hipStreamWaitEvent(sb, sd->fork, 0));
-    const size_t po_smem = sizeof(double) * potrf_smem_doubles(L.b);
-    const int nbr = L.b / 16, C32 = L.b / 32;
+    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, sc.err, 0);
+    LAUNCH(STILES_TK_OTHER, k_zero_ints, dim3(grid_for(L.nt * (int64_t)cstride)), dim3(NT), 0, st, cf,
+           L.nt * (int64_t)cstride);
+    // One launch per tile column, in order: POTRF of the diagonal tile, the
+    // panel TRSM below it and the trailing updates run as concurrent tasks of
+    // that launch, pipelined on the 16-column panels (k_column).
     for (int64_t J = 0; J < L.nt; ++J) {
-        const int s = L.s(J);
-        double* Xj = X64 + J * x64_per;
-        if (g_potrf_kind == 1)
-            LAUNCH(STILES_TK_POTRF, k_potrf_x64, dim3(1), dim3(NT), po_smem, sa, Lm + L.band(J, 0), (int64_t)L.b, L.b,
-                   Xj, ldp + 2 * J, winfo, J * (int64_t)L.b);
-        else
-            LAUNCH(STILES_TK_POTRF, k_potrf3, dim3(1), dim3(NT), 0, sa, Lm + L.band(J, 0), (int64_t)L.b, L.b, Xj,
-                   ldp + 2 * J, winfo, J * (int64_t)L.b);
-        HIPCHK(hipEventRecord(sd->po, sa));
-        const int tr_crit = s >= 1 ? nbr : 0;
-        const int tr_all = s * nbr + L.ap / 16;
-        const int up_crit = s >= 1 ? C32 * (C32 + 1) / 2 : 0;
-        const int up_all = upd32_count(L, J);
-        if (tr_crit > 0) {
-            if (J > 0) HIPCHK(hipStreamWaitEvent(sa, sd->up, 0));   // updates of column J-1 into tile (J+1, J)
-            LAUNCH(STILES_TK_TRSM, k_trsm16, dim3(tr_crit), dim3(NT), 0, sa, Lm, L, J, (const double*)Xj, 0);
-            HIPCHK(hipEventRecord(sd->tr, sa));
-            LAUNCH(STILES_TK_UPDATE, k_update32, dim3(up_crit), dim3(NT), 0, sa, Lm, L, J, 0);
-        }
-        HIPCHK(hipStreamWaitEvent(sb, sd->po, 0));
-        if (tr_all > tr_crit)
-            LAUNCH(STILES_TK_TRSM, k_trsm16, dim3(tr_all - tr_crit), dim3(NT), 0, sb, Lm, L, J, (const double*)Xj,
-                   tr_crit);
-        if (tr_crit > 0) HIPCHK(hipStreamWaitEvent(sb, sd->tr, 0));
-        if (up_all > up_crit)
-            LAUNCH(STILES_TK_UPDATE, k_update32, dim3(up_all - up_crit), dim3(NT), 0, sb, Lm, L, J, up_crit);
-        HIPCHK(hipEventRecord(sd->up, sb));
+        const int ntasks = 1 + col_tr_blocks(L, J) + col_up_blocks(L, J);
+        LAUNCH(STILES_TK_FACTOR, k_column, dim3((unsigned)std::min(ntasks, di.cus)), dim3(NT), 0, st, Lm, L, J,
+               Yd + J * y_per, cf + J * cstride, sc, ldp + 2 * J, (int*)winfo);
     }
-    if (g_potrf_kind != 1)
-        LAUNCH(STILES_TK_OTHER, k_zero_upper, dim3((unsigned)(8 * L.nt)), dim3(NT), 0, sb, Lm, L);
-    HIPCHK(hipEventRecord(sd->ja, sa));
-    HIPCHK(hipEventRecord(sd->jb, sb));
-    HIPCHK(hipStreamWaitEvent(st, sd->ja, 0));
-    HIPCHK(hipStreamWaitEvent(st, sd->jb, 0));
+    LAUNCH(STILES_TK_OTHER, k_zero_upper, dim3((unsigned)(8 * L.nt)), dim3(NT), 0, st, Lm, L);
     int nparts = (int)L.nt;
     if (L.ap > 0) {
         double* Cc = Lm + L.corner();
@@ -1163,7 +1216,7 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
         }
     }
     LAUNCH(STILES_TK_OTHER, k_factor_final, dim3(1), dim3(64), 0, st, (const double*)ldp, nparts, (const int*)winfo,
-                       logdet, (int*)info);
+                       (const int*)sc.err, logdet, (int*)info);
     return 0;
 }
 

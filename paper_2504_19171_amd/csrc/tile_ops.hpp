@@ -236,88 +236,3 @@ __device__ inline void trtri_tile(const double* L, int64_t ldl, double* X, int64
     *bad = s_bad;
 }
 
-// Inverses of the 64 x 64 diagonal blocks of the m x m lower-triangular L
-// (column-major, leading dimension ldl), m a multiple of 64, m <= 256.
-// Block g goes to X64 + g*4096 (64 x 64 column-major); entries above its
-// 16 x 16 block diagonal are not written (readers use only the lower blocks).
-// Same recurrence as trtri_tile, restricted to pairs of 16-blocks inside one
-// 64-block: at most three rounds of MFMA tasks.
-__device__ inline void inv64_rounds(const double* L, int64_t ldl, double* X64, int m, double* smem);
-
-__device__ inline void inv64_blocks(const double* L, int64_t ldl, double* X64, int m, double* smem) {
-    const int t = threadIdx.x;
-    const int lane = t & 63;
-    const int wv = t >> 6;
-    const int nblk = m / 16;
-    // 1. diagonal 16 x 16 blocks, one column per lane
-    for (int base = 0; base < nblk; base += 4) {
-        const int blk = base + wv;
-        if (blk < nblk && lane < 16) {
-            const int o = 16 * blk;
-            const int j = lane;
-            double* Xg = X64 + (int64_t)(blk >> 2) * 4096;
-            const int xo = 16 * (blk & 3);
-            double x[16];
-#pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                double s = (i == j) ? 1.0 : 0.0;
-#pragma unroll
-                for (int k = 0; k < i; ++k) s -= L[(o + i) + (int64_t)(o + k) * ldl] * x[k];
-                x[i] = (i >= j) ? s / L[(o + i) + (int64_t)(o + i) * ldl] : 0.0;
-            }
-#pragma unroll
-            for (int i = 0; i < 16; ++i) Xg[(xo + i) + (xo + j) * 64] = x[i];
-        }
-    }
-    __syncthreads();
-    inv64_rounds(L, ldl, X64, m, smem);
-}
-
-// Steps 2 of inv64_blocks alone (the diagonal 16 x 16 inverses already in
-// X64); smem: 4 x 16 x TO_LDD doubles.  Ends with a barrier.
-__device__ inline void inv64_rounds(const double* L, int64_t ldl, double* X64, int m, double* smem) {
-    const int t = threadIdx.x;
-    const int lane = t & 63;
-    const int wv = t >> 6;
-    // 2. block diagonals inside each 64-block: X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ
-    double* sT = smem + wv * 16 * TO_LDD;
-    const int li = lane & 15, lk = lane >> 4;
-    const int ng = m / 64;
-    for (int dlt = 1; dlt < 4; ++dlt) {
-        const int per = 4 - dlt;         // tasks per 64-block
-        const int ntask = per * ng;
-        for (int base = 0; base < ntask; base += 4) {
-            const int tk = base + wv;
-            const bool act = tk < ntask;
-            const int g = act ? tk / per : 0, J = act ? tk % per : 0, I = J + dlt;
-            const double* Lg = L + 64 * g + (int64_t)64 * g * ldl;
-            double* Xg = X64 + (int64_t)g * 4096;
-            dbl4 acc = {0.0, 0.0, 0.0, 0.0};
-            if (act) {
-                for (int K = J; K < I; ++K) {
-#pragma unroll
-                    for (int kk = 0; kk < 16; kk += 4) {
-                        const double av = Lg[(16 * I + li) + (int64_t)(16 * K + kk + lk) * ldl];
-                        const double bv = Xg[(16 * K + kk + lk) + (16 * J + li) * 64];
-                        acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
-                    }
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) sT[li * TO_LDD + 4 * r + lk] = acc[r];
-            }
-            __syncthreads();
-            if (act) {
-                dbl4 out = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int kk = 0; kk < 16; kk += 4) {
-                    const double av = -Xg[(16 * I + li) + (16 * I + kk + lk) * 64];
-                    const double bv = sT[li * TO_LDD + kk + lk];
-                    out = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, out, 0, 0, 0);
-                }
-#pragma unroll
-                for (int r = 0; r < 4; ++r) Xg[(16 * I + 4 * r + lk) + (16 * J + li) * 64] = out[r];
-            }
-            __syncthreads();
-        }
-    }
-}
