@@ -38,10 +38,8 @@
  * - `stream` is a hipStream_t (NULL = the default stream).  Every call only
  *   enqueues work on `stream` and returns; results are ready when the stream
  *   is.  Calls on different streams may overlap if they use different buffers
- *   and workspaces.  stiles_factor forks part of its work onto one internal
- *   stream per device (default priority, created with a few events on first
- *   use and kept until the process ends) and joins it back into `stream`
- *   before its last kernel, so `stream` still orders everything.
+ *   and workspaces.  The library creates no streams or events of its own
+ *   (except the timing events of stiles_timing_enable).
  * - Return value: 0 when the work was enqueued; -i when argument i (1-based)
  *   is invalid; STILES_EHIP when a HIP call failed.  Numerical outcomes are
  *   reported in the device `info` word (see stiles_factor / stiles_selinv).
@@ -147,12 +145,12 @@ int stiles_selinv(const double* L, double* Sigma, int64_t n, int64_t bandwidth, 
  * drops events not collected yet.  Thread-safe; costs two event records per
  * launch while enabled.
  */
-#define STILES_TK_POTRF 0      /* factor: diagonal tiles (POTRF, with their TRTRI) */
-#define STILES_TK_TRSM 1       /* factor: panel TRSM */
-#define STILES_TK_UPDATE 2     /* factor: trailing SYRK/GEMM updates */
+#define STILES_TK_POTRF 0      /* factor: the corner's diagonal blocks (POTRF) */
+#define STILES_TK_TRSM 1       /* factor: reserved (panel TRSM runs inside the tile-column launches) */
+#define STILES_TK_UPDATE 2     /* factor: reserved (trailing updates run inside the tile-column launches) */
 #define STILES_TK_PHASE1 3     /* selinv: Phase 1 (TRTRI, TRMM, LAUUM) */
 #define STILES_TK_PHASE2 4     /* selinv: Phase 2 (persistent kernel) */
-#define STILES_TK_FACTOR 5     /* factor: persistent kernel */
+#define STILES_TK_FACTOR 5     /* factor: one launch per band tile column (POTRF + TRSM + updates) */
 #define STILES_TK_OTHER 6      /* pack, copies, corner, finalization */
 #define STILES_TK_COUNT 7
 int stiles_timing_enable(int on);

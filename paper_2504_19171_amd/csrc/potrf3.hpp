@@ -1,7 +1,7 @@
 // Cholesky of one diagonal tile (m <= 256, m a multiple of 64) by one
-// workgroup of 4 wavefronts, left-looking over 16-column panels with a
+// workgroup of 1 + P3_PW wavefronts, left-looking over 16-column panels with a
 // one-panel lookahead:
-//   - wavefronts 1..3 own the 16 x 16 row tiles I = w, w+3, ... of every
+//   - wavefronts 1..P3_PW own the 16 x 16 row tiles I = w, w+P3_PW, ... of every
 //     panel; the reduced current panel sits in LDS in transposed MFMA form
 //     (lane (i, k) reads C[16I + i][c0 + 4r + k], the layout the matrix cores
 //     take as the B operand, so the panel solve needs no shuffle);
@@ -19,7 +19,9 @@
 #include "tile_ops.hpp"
 
 #define P3_LD 17
-#define P3_SLOTS 5   // row tiles I >= 1 per wavefront: 15 / 3
+#define P3_PW 3                                    // panel wavefronts (1 .. P3_PW); wavefront 0 runs the diagonal chain
+#define P3_NT (64 * (1 + P3_PW))                   // threads of a workgroup running potrf3
+#define P3_SLOTS ((15 + P3_PW - 1) / P3_PW)        // row tiles I >= 1 per panel wavefront
 #define P3_POOL 65   // 16 x 16 tiles of L alive at once at m = 256 (checked by p3_make_slots)
 
 struct P3Smem {
@@ -253,43 +255,27 @@ __device__ inline int p3_slot(uint32_t tab, int I, int k) {
 // (I >= np) works on a clamped copy, and a slot with nothing to do works on
 // whatever its indices give, and neither stores anything.
 
-// S(p): L_Ip^T = Y C_Ip^T for the tiles I > p, in place in the pool (each
-// tile read whole before it is written) and to global memory (device-coherent
-// stores: a concurrent kernel reads them).
-template <int S0>
-__device__ __forceinline__ void p3_solve_slots(P3Smem& sm, double* Mw, int ldi, uint32_t tab, int w, int np, int p,
-                                               int lane, int li, int lk) {
-    constexpr int NS = P3_SLOTS - S0;
-    const int c0 = 16 * p;
-    double* X[NS];
-    dbl4 o[NS];
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        X[q] = sm.pool[p3_slot(tab, imin_(3 * (S0 + q) + w, np - 1), p)];
-        o[q] = dbl4{0.0, 0.0, 0.0, 0.0};
-    }
-    double yv[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) yv[r] = sm.Y[li * P3_LD + 4 * r + lk];
+// L_Ip^T = Y C_Ip^T for one tile I > p, in place in the pool (the wavefront
+// reads the whole tile before it writes it) and to global memory
+// (device-coherent stores: a concurrent TRSM reads them).
+__device__ inline void p3_solve_tile(P3Smem& sm, double* Mw, int ldi, uint32_t tab, int I, int p, int lane, int li,
+                                     int lk) {
+    double* X = sm.pool[p3_slot(tab, I, p)];
+    dbl4 o = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < 4; ++r)
+        o = __builtin_amdgcn_mfma_f64_16x16x4f64(sm.Y[li * P3_LD + 4 * r + lk], X[r * 64 + lane], o, 0, 0, 0);
 #pragma unroll
-        for (int q = 0; q < NS; ++q) o[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[r], X[q][r * 64 + lane], o[q], 0, 0, 0);
-#pragma unroll
-    for (int q = 0; q < NS; ++q) {
-        const int I = 3 * (S0 + q) + w;
-        if (I > p && I < np) {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                st_coh_s(Mw, (uint32_t)((16 * I + li) + (c0 + 4 * r + lk) * ldi), o[q][r]);
-                X[q][(4 * r + lk) * 16 + li] = o[q][r];
-            }
-        }
+    for (int r = 0; r < 4; ++r) {
+        st_coh_s(Mw, (uint32_t)((16 * I + li) + (16 * p + 4 * r + lk) * ldi), o[r]);
+        X[(4 * r + lk) * 16 + li] = o[r];
     }
 }
 
-// U(p), p + 2 < np: panel p into the tiles I >= p+2 of panel p+1 (nxt ->
-// pool, transposed MFMA form, for S(p+1)); then the tiles I >= p+2 of panel
+// U(p), p + 2 < np: first the solves of this wavefront's tiles I >= p+3 of
+// panel p (L_Ip^T = Y C_Ip^T, in place; S(p) did only the tiles p+1 and p+2,
+// which other wavefronts read); then panel p into the tiles I >= p+2 of panel
+// p+1 (nxt -> pool, transposed MFMA form, for S(p+1)); then the tiles I >= p+2 of panel
 // p+2: raw values from global memory into nxt (the only global reads of the
 // loop, in flight during the products), reduced over the panels 0..p from the
 // pool (products accumulated apart, subtracted at the end).  The panels go in
@@ -297,14 +283,44 @@ __device__ __forceinline__ void p3_solve_slots(P3Smem& sm, double* Mw, int ldi, 
 // basic block; the owner of tile p+2 hands its diagonal block to wavefront 0
 // through Dn.
 template <int S0>
-__device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& sm, const double* Mc, int ldi,
-                                                uint32_t tab, int w, int np, int p, int lane, int li, int lk) {
+__device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& sm, const double* Mc, double* Mw,
+                                                int ldi, uint32_t tab, int w, int np, int p, int lane, int li,
+                                                int lk) {
     constexpr int NS = P3_SLOTS - S0;
     const int c2 = 16 * (p + 2);
     const int lo = lk * 16 + li;
     int Is[NS];
 #pragma unroll
-    for (int q = 0; q < NS; ++q) Is[q] = imin_(3 * (S0 + q) + w, np - 1);
+    for (int q = 0; q < NS; ++q) Is[q] = imin_(P3_PW * (S0 + q) + w, np - 1);
+    {
+        // every slot multiplies; only the tiles I >= p+3 are stored
+        double* X[NS];
+        dbl4 o[NS];
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            X[q] = sm.pool[p3_slot(tab, Is[q], p)];
+            o[q] = dbl4{0.0, 0.0, 0.0, 0.0};
+        }
+        double yv[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) yv[r] = sm.Y[li * P3_LD + 4 * r + lk];
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+#pragma unroll
+            for (int q = 0; q < NS; ++q)
+                o[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(yv[r], X[q][r * 64 + lane], o[q], 0, 0, 0);
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int I = P3_PW * (S0 + q) + w;
+            if (I >= p + 3 && I < np) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    st_coh_s(Mw, (uint32_t)((16 * I + li) + (16 * p + 4 * r + lk) * ldi), o[q][r]);
+                    X[q][(4 * r + lk) * 16 + li] = o[q][r];
+                }
+            }
+        }
+    }
     {
         const double* L1 = sm.pool[p3_slot(tab, p + 1, p)];
         double av[4];
@@ -318,7 +334,7 @@ __device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& s
                                                                    nxt[S0 + q], 0, 0, 0);
 #pragma unroll
         for (int q = 0; q < NS; ++q) {
-            const int I = 3 * (S0 + q) + w;
+            const int I = P3_PW * (S0 + q) + w;
             if (I >= p + 2 && I < np) {
                 double* X = sm.pool[p3_slot(tab, I, p + 1)];
 #pragma unroll
@@ -370,10 +386,23 @@ __device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& s
 #pragma unroll
     for (int q = 0; q < NS; ++q) {
         nxt[S0 + q] -= red[q];
-        if (3 * (S0 + q) + w == p + 2) {
+        if (P3_PW * (S0 + q) + w == p + 2) {
 #pragma unroll
             for (int r = 0; r < 4; ++r) sm.Dn[(p + 2) & 1][(4 * r + lk) * P3_LD + li] = nxt[S0 + q][r];
         }
+    }
+}
+
+// p3_update_slots<s0> for a run-time s0 < P3_SLOTS.
+template <int S0 = 0>
+__device__ __forceinline__ void p3_update_dispatch(int s0, dbl4 (&nxt)[P3_SLOTS], P3Smem& sm, const double* Mc,
+                                                   double* Mw, int ldi, uint32_t tab, int w, int np, int p, int lane,
+                                                   int li, int lk) {
+    if constexpr (S0 == P3_SLOTS - 1) {
+        p3_update_slots<S0>(nxt, sm, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
+    } else {
+        if (s0 == S0) p3_update_slots<S0>(nxt, sm, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
+        else p3_update_dispatch<S0 + 1>(s0, nxt, sm, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
     }
 }
 
@@ -394,12 +423,14 @@ __device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& s
 // the end.)
 //
 // Software pipeline over the 16-column panels p, two phases per panel:
-//   S(p): L_pp and Y_pp go out; wavefronts 1..3 solve their tiles of panel p
-//         (L_Ip = C_Ip Y^T) in place in the LDS pool and to global memory;
+//   S(p): L_pp and Y_pp go out; the tiles (p+1, p) and (p+2, p), which other
+//         wavefronts need next, are solved (L_Ip = C_Ip Y^T) in place in the
+//         LDS pool and to global memory by their owners;
 //   U(p): wavefront 0 forms the next diagonal block D_{p+1} = Dn - L_{p+1,p}
-//         L_{p+1,p}^T and factors it (factor16), while wavefronts 1..3 add
-//         panel p into the tiles of panel p+1 (into the pool, solved by
-//         S(p+1)) and reduce the tiles of panel p+2 over panels 0..p; the
+//         L_{p+1,p}^T and factors it (factor16), while the panel wavefronts solve
+//         their other tiles of panel p, add panel p into the tiles of panel
+//         p+1 (into the pool, solved from S(p+1) on) and reduce the tiles of
+//         panel p+2 over panels 0..p; the
 //         owner of tile p+2 hands its diagonal block to wavefront 0 through Dn
 //         (by parity).
 // Every tile of L stays in the LDS pool from its reduction to its last use,
@@ -409,15 +440,18 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
                               double* lc_out, int* fpo) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
-    const int np = m / 16;
+    // np and ldi opaque here: the offsets derived from them are formed in this
+    // task, not hoisted to the start of a kernel that runs other tasks too
+    // (where they would only occupy registers)
+    int np = m / 16, ldi = (int)ld;
+    asm volatile("" : "+s"(np), "+s"(ldi));
     const double* Mc = uniform_ptr(M);   // with unsigned 32-bit offsets: scalar base + vector offset loads
     double* Mw = (double*)Mc;
-    const int ldi = (int)ld;
     int fail = -1;
     const uint32_t tab = p3_slot_pack.w[np / 4 - 1][lane];
     // panel 0 into the pool, transposed MFMA form: [r*64 + lane] = C[16I + li][4r + lk];
     // D_0 = tile (0, 0); Y's upper part stays 0 from here on
-    {
+    if (w < 4) {   // 256 threads: one element of each 16 x 16 tile each
         double v[16];
         const int q = threadIdx.x, r = q >> 6, ln = q & 63;
 #pragma unroll
@@ -426,20 +460,18 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
 #pragma unroll
         for (int I = 1; I < 16; ++I)
             if (I < np) sm.pool[p3_slot(tab, I, 0)][q] = v[I];
-    }
-    {
         const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
         sm.D[j * P3_LD + i] = ld_s(Mc, (uint32_t)(i + j * ldi));
     }
     for (int e = threadIdx.x; e < 16 * P3_LD; e += 256) sm.Y[e] = 0.0;
-    // wavefronts 1..3 own the row tiles I = 3s + w >= 1 of every panel
+    // panel wavefronts w = 1..P3_PW own the row tiles I = P3_PW s + w >= 1 of every panel
     dbl4 nxt[P3_SLOTS];
     // raw tiles of panel 1 (nothing to reduce yet); tile 1 is owned by
     // wavefront 1, slot 0, and goes to Dn
     if (w != 0) {
 #pragma unroll
         for (int s = 0; s < P3_SLOTS; ++s) {
-            const int I = imin_(3 * s + w, np - 1);
+            const int I = imin_(P3_PW * s + w, np - 1);
 #pragma unroll
             for (int r = 0; r < 4; ++r) nxt[s][r] = ld_s(Mc, (uint32_t)((16 * I + li) + (16 + 4 * r + lk) * ldi));
         }
@@ -470,15 +502,10 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
                 st_coh_s(Yg, (uint32_t)(i + 16 * j), yv[q]);
             }
         } else {
-            // slots s >= s1 hold the tiles I > p
-            const int s1 = imin_(P3_SLOTS - 1, imax_(0, (p + 1 - w + 2) / 3));
-            switch (s1) {
-                case 0: p3_solve_slots<0>(sm, Mw, ldi, tab, w, np, p, lane, li, lk); break;
-                case 1: p3_solve_slots<1>(sm, Mw, ldi, tab, w, np, p, lane, li, lk); break;
-                case 2: p3_solve_slots<2>(sm, Mw, ldi, tab, w, np, p, lane, li, lk); break;
-                case 3: p3_solve_slots<3>(sm, Mw, ldi, tab, w, np, p, lane, li, lk); break;
-                default: p3_solve_slots<4>(sm, Mw, ldi, tab, w, np, p, lane, li, lk); break;
-            }
+            // the tiles other wavefronts read in U(p): (p+1, p) and (p+2, p)
+            // (each owned by a different wavefront); the rest waits for U(p)
+            if (p + 1 < np && ((p + 1) - w) % P3_PW == 0) p3_solve_tile(sm, Mw, ldi, tab, p + 1, p, lane, li, lk);
+            if (p + 2 < np && ((p + 2) - w) % P3_PW == 0) p3_solve_tile(sm, Mw, ldi, tab, p + 2, p, lane, li, lk);
         }
         p3_bar_lds();   // panel p of L in the pool (the global stores stay in flight)
         if (p + 1 == np) break;
@@ -500,14 +527,8 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
             p3_factor16(sm, c0 + 16, fail);
         } else if (p + 2 < np) {
             // slots s >= s0 hold the tiles I >= p+2
-            const int s0 = imin_(P3_SLOTS - 1, imax_(0, (p + 2 - w + 2) / 3));
-            switch (s0) {
-                case 0: p3_update_slots<0>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
-                case 1: p3_update_slots<1>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
-                case 2: p3_update_slots<2>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
-                case 3: p3_update_slots<3>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
-                default: p3_update_slots<4>(nxt, sm, Mc, ldi, tab, w, np, p, lane, li, lk); break;
-            }
+            const int s0 = imin_(P3_SLOTS - 1, imax_(0, (p + 2 - w + P3_PW - 1) / P3_PW));
+            p3_update_dispatch(s0, nxt, sm, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
         }
         // D, Y of p+1; panel p+1 in the pool; Dn; and the stores of panel p
         // complete, so it is announced.

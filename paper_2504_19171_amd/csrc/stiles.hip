@@ -207,7 +207,7 @@ __device__ inline bool tr_panel(double* C, int ld, const double* Ljj, const doub
     C = (double*)uniform_ptr(C);
     Ljj = uniform_ptr(Ljj);
     Yd = uniform_ptr(Yd);
-    for (int e = threadIdx.x; e < b * TR_LD; e += NT) sm.R[e] = 0.0;
+    for (int e = threadIdx.x; e < b * TR_LD; e += blockDim.x) sm.R[e] = 0.0;
     auto ldL = [&](uint32_t idx) { return coh ? ld_coh_s(Ljj, idx) : ld_s(Ljj, idx); };
     // A operands of step s for this wavefront: -L_{s,p'} for p' = w + 4t (the
     // tile column clamped into the finished part; its product is then with a
@@ -244,20 +244,23 @@ __device__ inline bool tr_panel(double* C, int ld, const double* Ljj, const doub
         dbl4 cnext;
 #pragma unroll
         for (int r = 0; r < 4; ++r) cnext[r] = ld_s(C, (uint32_t)(li + (16 * pn + 4 * r + lk) * ld));
-        // this wavefront's part of Z_p^T
-        dbl4 z;
+        // this wavefront's part of Z_p^T (wavefronts past the fourth, if the
+        // workgroup has them, only keep the barriers)
+        if (w < 4) {
+            dbl4 z;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) z[r] = (w == 0) ? cn[r] : 0.0;
+            for (int r = 0; r < 4; ++r) z[r] = (w == 0) ? cn[r] : 0.0;
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int p2 = imin_(w + 4 * t, np - 1);
+            for (int t = 0; t < 4; ++t) {
+                const int p2 = imin_(w + 4 * t, np - 1);
 #pragma unroll
-            for (int kk = 0; kk < 4; ++kk)
-                z = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[t][kk], sm.R[(16 * p2 + 4 * kk + lk) * TR_LD + li], z, 0,
-                                                         0, 0);
+                for (int kk = 0; kk < 4; ++kk)
+                    z = __builtin_amdgcn_mfma_f64_16x16x4f64(acur[t][kk], sm.R[(16 * p2 + 4 * kk + lk) * TR_LD + li], z,
+                                                             0, 0, 0);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) sm.P[w][r * 64 + lane] = z[r];
         }
-#pragma unroll
-        for (int r = 0; r < 4; ++r) sm.P[w][r * 64 + lane] = z[r];
         __syncthreads();
         if (w == 0) {
             // Z_p^T in the D layout is the B operand of R_p^T = Y_p Z_p^T as it stands
@@ -391,9 +394,10 @@ __device__ inline bool col_wait(const Sched& sc, const int* flag, int n, int tar
 }
 
 // One 64 x 64 target block, accumulated one 16-column panel of tile column J
-// at a time as the TRSM steps of its rows are announced.  Wavefront w owns
-// the 32 x 32 quarter (w/2, w%2), four 16 x 16 tiles; tiles past the valid
-// rows, and tiles above the diagonal of a diagonal block, are not stored.
+// at a time as the TRSM steps of its rows are announced.  Wavefront w < 4
+// owns the 32 x 32 quarter (w/2, w%2), four 16 x 16 tiles; tiles past the
+// valid rows, and tiles above the diagonal of a diagonal block, are not
+// stored (a fifth wavefront's quarter lies past the block: it stores nothing).
 __device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, const Sched& sc, int* sh) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
@@ -461,7 +465,7 @@ union ColSmem {
     P3Smem po;
     TrSmem tr;
 };
-__global__ __launch_bounds__(NT) void k_column(double* Lm, Lay L, int64_t J, double* Yd, int* cf, Sched sc,
+__global__ __launch_bounds__(P3_NT) void k_column(double* Lm, Lay L, int64_t J, double* Yd, int* cf, Sched sc,
                                                double* ldp, int* info) {
     __shared__ ColSmem sm;
     __shared__ int sh;
@@ -1186,7 +1190,7 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     // that launch, pipelined on the 16-column panels (k_column).
     for (int64_t J = 0; J < L.nt; ++J) {
         const int ntasks = 1 + col_tr_blocks(L, J) + col_up_blocks(L, J);
-        LAUNCH(STILES_TK_FACTOR, k_column, dim3((unsigned)std::min(ntasks, di.cus)), dim3(NT), 0, st, Lm, L, J,
+        LAUNCH(STILES_TK_FACTOR, k_column, dim3((unsigned)std::min(ntasks, di.cus)), dim3(P3_NT), 0, st, Lm, L, J,
                Yd + J * y_per, cf + J * cstride, sc, ldp + 2 * J, (int*)winfo);
     }
     LAUNCH(STILES_TK_OTHER, k_zero_upper, dim3((unsigned)(8 * L.nt)), dim3(NT), 0, st, Lm, L);
