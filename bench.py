@@ -21,6 +21,28 @@ sys.path.insert(0, ROOT)
 
 METRIC = "FP64 factor+selinv GFLOP/s & solves/s, batched vs plain; p50/p99 latency"
 PEAK_F64_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
+
+# HBM bytes per launch of the dominant kernel kind, from rocprofv3 FETCH_SIZE /
+# WRITE_SIZE runs scaled by a copy of known size (profiles/k_column_large_hbm_traffic.md),
+# valid only for the kernel sources they were taken with (sha256 prefix of csrc/*)
+# and the workload named.
+MEASURED_TRAFFIC = {("factor", "large"): {"bytes_per_launch": 30.49e6, "sources": "a4892fa66a8b6854"}}
+
+
+def sources_hash() -> str:
+    """sha256 prefix of the kernel sources with // comments and blank lines removed."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for f in sorted(glob.glob(os.path.join(here, "paper_2504_19171_amd", "csrc", "*"))):
+        h.update(os.path.basename(f).encode())
+        with open(f, encoding="utf-8") as fh:
+            for line in fh:
+                code = line.split("//", 1)[0].strip()
+                if code:
+                    h.update(code.encode() + b"\n")
+    return h.hexdigest()[:16]
 PEAK_HBM_GBS = 8000.0
 
 
@@ -145,8 +167,10 @@ def main() -> int:
     dom = max((k for k in per_kind if k != "other"), key=lambda k: per_kind[k][0])
     dom_ms, dom_launches = per_kind[dom]
     achieved = kf[dom] * args.steps / (dom_ms / 1e3) / 1e12 if dom_ms > 0 else 0.0
+    mt = MEASURED_TRAFFIC.get((dom, args.workload))
+    traffic = mt["bytes_per_launch"] if mt and mt["sources"] == sources_hash() else None
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": None,
+                "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": traffic,
                 "launches_per_step": dom_launches // max(args.steps, 1),
                 "avg_launch_us": round(dom_ms * 1e3 / max(dom_launches, 1), 2)}
     breakdown = {k: {"ms_per_step": round(v[0] / args.steps, 3),

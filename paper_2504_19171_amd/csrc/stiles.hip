@@ -189,7 +189,7 @@ __global__ __launch_bounds__(NT) void k_zero_upper(double* Lm, Lay L) {
 // LDS ([column][row]) and is zero where not yet computed, so a product with a
 // panel that is not there yet adds nothing and the loop has no branches.
 //
-// Concurrent mode (fpo != nullptr): L_JJ is being factored by k_potrf3 at the
+// Concurrent mode (fpo != nullptr): L_JJ is being factored (potrf3) at the
 // same time; step p waits until *fpo > p, reads L and Y with device-coherent
 // loads, writes R with device-coherent stores and raises *ftr after each step.
 #define TR_LD 16
