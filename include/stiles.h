@@ -136,6 +136,59 @@ int stiles_selinv(const double* L, double* Sigma, int64_t n, int64_t bandwidth, 
                   void* stream);
 
 /*
+ * Batched form: `count` independent matrices, each with its own n, bandwidth,
+ * arrow and tile, factored (or inverted) together.  The paper treats one
+ * matrix per call (Sec. III); here every launch of the single-matrix path
+ * covers all the matrices that have work in it, each on its own share of the
+ * workgroups with its own tickets and counters, so a batch of small matrices
+ * fills the device.  The tasks and their arithmetic are those of stiles_factor
+ * and stiles_selinv on each matrix alone: results are identical bit for bit.
+ *
+ * The tile-column launches run in step across the batch (launch J covers
+ * column J of every matrix with N > J), so the batch takes about as long as
+ * its longest matrix, and a batch with one tile size runs best.
+ *
+ * items (host array of `count` entries, read during the call only):
+ *   n, bandwidth, arrow, tile   as for stiles_layout_init; reserved must be 0
+ *   A       device, tile layout input of stiles_factor_batched
+ *   L       device, L (output of the factor, input of the selinv); may equal A
+ *   Sigma   device, Sigma output of stiles_selinv_batched (ignored by the
+ *           factor); must not alias L
+ *   logdet  device, one double (factor)
+ *   info    device, two int32: [0] as stiles_factor's info, [1] as
+ *           stiles_selinv's info
+ * workspace  device, at least stiles_batch_workspace_bytes(items, count); one
+ *           workspace serves both calls (contents on entry are ignored).
+ * The calls copy a small table of the matrices from host memory into the
+ * workspace with hipMemcpyAsync on `stream`; as the source is pageable memory,
+ * that copy may wait for work already queued on the stream.
+ * Returns 0; -1 if items is NULL or an item is invalid (its layout, a NULL
+ * pointer, reserved != 0, or for the selinv Sigma NULL or equal to L); -2 if
+ * count < 1; -3 / -4 for the workspace and its size; STILES_EHIP.
+ */
+typedef struct stiles_batch_item {
+    int64_t n, bandwidth, arrow;
+    int32_t tile;
+    int32_t reserved;
+    const double* A;
+    double* L;
+    double* Sigma;
+    double* logdet;
+    int32_t* info;
+} stiles_batch_item;
+
+/* Workspace size in bytes for a batch (host only); 0 if an item is invalid. */
+size_t stiles_batch_workspace_bytes(const stiles_batch_item* items, int32_t count);
+
+/* stiles_factor on every item: L and log det of each matrix. */
+int stiles_factor_batched(const stiles_batch_item* items, int32_t count, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/* stiles_selinv on every item: Sigma on the tile pattern of each L. */
+int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* workspace,
+                          size_t workspace_bytes, void* stream);
+
+/*
  * Per-kernel timing with HIP events (tracing support, not needed for results).
  * While enabled, every kernel the library enqueues is bracketed by a pair of
  * HIP events recorded on the same stream.  stiles_timing_collect() waits for

@@ -22,6 +22,7 @@
 #include "potrf3.hpp"
 
 #define NT 256
+#define WS_HEAD 256  // bytes reserved at the start of every workspace (info and scheduler words)
 
 // ---------------------------------------------------------------------------
 // Layout
@@ -103,12 +104,13 @@ __global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, cons
     }
 }
 
-// Zero the band tiles (J+d, J) with J+d >= N (outside the matrix).
-__global__ __launch_bounds__(NT) void k_zero_unused(double* T, Lay L) {
+// Zero the band tiles (J+d, J) with J+d >= N (outside the matrix); block bid
+// of nblk.
+__device__ inline void zero_unused_body(double* T, const Lay& L, int bid, int nblk) {
     const int64_t b2 = (int64_t)L.b * L.b;
     const int64_t ntail = (int64_t)L.bt * (L.bt + 1) / 2;  // tiles J+d >= N
     const int64_t tot = ntail * b2;
-    for (int64_t idx = blockIdx.x * (int64_t)NT + threadIdx.x; idx < tot; idx += (int64_t)gridDim.x * NT) {
+    for (int64_t idx = bid * (int64_t)NT + threadIdx.x; idx < tot; idx += (int64_t)nblk * NT) {
         const int64_t t = idx / b2, e = idx % b2;
         // enumerate (J, d) with J = N-1-m, d = m+1..B, m = 0..B-1
         int64_t m = 0, cnt = t;
@@ -117,6 +119,7 @@ __global__ __launch_bounds__(NT) void k_zero_unused(double* T, Lay L) {
         T[L.band(J, (int)d) + e] = 0.0;
     }
 }
+__global__ __launch_bounds__(NT) void k_zero_unused(double* T, Lay L) { zero_unused_body(T, L, blockIdx.x, gridDim.x); }
 
 // ---------------------------------------------------------------------------
 // Factor kernels
@@ -125,9 +128,8 @@ __global__ __launch_bounds__(NT) void k_zero_unused(double* T, Lay L) {
 // POTRF of one m x m diagonal block (m <= 256), optional TRTRI of the result
 // into X, log det partial into ldp[0..1], first failing column into *info
 // (atomicMin of the 1-based global column col_base + c + 1).
-__global__ __launch_bounds__(NT) void k_potrf(double* M, int64_t ld, int m, double* X, int64_t ldx,
-                                             double* ldp, int* info, int64_t col_base) {
-    extern __shared__ double smem[];
+__device__ inline void potrf_body(double* M, int64_t ld, int m, double* X, int64_t ldx, double* ldp, int* info,
+                                  int64_t col_base, double* smem) {
     int fail;
     double s, c;
     potrf_tile(M, ld, m, smem, &fail, &s, &c);
@@ -141,6 +143,11 @@ __global__ __launch_bounds__(NT) void k_potrf(double* M, int64_t ld, int m, doub
         int bad;
         trtri_tile(M, ld, X, ldx, m, smem, &bad);
     }
+}
+__global__ __launch_bounds__(NT) void k_potrf(double* M, int64_t ld, int m, double* X, int64_t ldx,
+                                             double* ldp, int* info, int64_t col_base) {
+    extern __shared__ double smem[];
+    potrf_body(M, ld, m, X, ldx, ldp, info, col_base, smem);
 }
 
 // In place: columns are produced last block first, so every column block
@@ -170,13 +177,14 @@ __global__ __launch_bounds__(NT) void k_trsm_generic(double* C, int64_t ld, int 
 // Strict upper triangles of the band diagonal tiles set to 0 (the layout's
 // convention for L; the diagonal-tile POTRF leaves them, as nothing in the
 // factorization reads them).  Eight workgroups per tile, b/8 columns each.
-__global__ __launch_bounds__(NT) void k_zero_upper(double* Lm, Lay L) {
-    const int64_t J = blockIdx.x >> 3;
-    const int cw = L.b / 8, c0 = (int)(blockIdx.x & 7) * cw;
+__device__ inline void zero_upper_body(double* Lm, const Lay& L, int bid) {
+    const int64_t J = bid >> 3;
+    const int cw = L.b / 8, c0 = (bid & 7) * cw;
     double* T = Lm + L.band(J, 0);
     for (int c = c0; c < c0 + cw; ++c)
         for (int i = threadIdx.x; i < c; i += NT) T[i + (int64_t)c * L.b] = 0.0;
 }
+__global__ __launch_bounds__(NT) void k_zero_upper(double* Lm, Lay L) { zero_upper_body(Lm, L, blockIdx.x); }
 
 // Panel TRSM of one 16-row block C (16 x b, leading dimension ld), R = C
 // L_JJ^{-T} in place, one 16-column panel p per step:
@@ -465,10 +473,8 @@ union ColSmem {
     P3Smem po;
     TrSmem tr;
 };
-__global__ __launch_bounds__(P3_NT) void k_column(double* Lm, Lay L, int64_t J, double* Yd, int* cf, Sched sc,
-                                               double* ldp, int* info) {
-    __shared__ ColSmem sm;
-    __shared__ int sh;
+__device__ inline void col_run(ColSmem& sm, int& sh, double* Lm, const Lay& L, int64_t J, double* Yd, int* cf,
+                               const Sched& sc, double* ldp, int* info) {
     const int ntr = col_tr_blocks(L, J);
     const int ntasks = 1 + ntr + col_up_blocks(L, J);
     const int nbr = L.b / 16, s = L.s(J);
@@ -501,6 +507,12 @@ __global__ __launch_bounds__(P3_NT) void k_column(double* Lm, Lay L, int64_t J, 
         }
     }
 }
+__global__ __launch_bounds__(P3_NT) void k_column(double* Lm, Lay L, int64_t J, double* Yd, int* cf, Sched sc,
+                                               double* ldp, int* info) {
+    __shared__ ColSmem sm;
+    __shared__ int sh;
+    col_run(sm, sh, Lm, L, J, Yd, cf, sc, ldp, info);
+}
 
 // C (rows x rows, lower blocks) -= P P^T, P rows x K (generic, corner blocking).
 __global__ __launch_bounds__(NT) void k_syrk_generic(double* C, int64_t ldc, const double* P,
@@ -522,9 +534,8 @@ __global__ void k_zero_block(double* C, int64_t ld, int rows, int cols) {
 }
 
 // Final log det (Neumaier sum of the per-block partials, in order) and info.
-__global__ void k_factor_final(const double* ldp, int nparts, const int* info_ws, const int* err, double* logdet,
-                               int* info) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+__device__ inline void factor_final_body(const double* ldp, int nparts, const int* info_ws, const int* err,
+                                         double* logdet, int* info) {
     double s = 0.0, c = 0.0;
     for (int i = 0; i < nparts; ++i) {
         neumaier(s, c, ldp[2 * i]);
@@ -534,6 +545,11 @@ __global__ void k_factor_final(const double* ldp, int nparts, const int* info_ws
     *info = (f == 0x7fffffff) ? 0 : f;
     *logdet = (f == 0x7fffffff) ? (s + c) : __builtin_nan("");
 }
+__global__ void k_factor_final(const double* ldp, int nparts, const int* info_ws, const int* err, double* logdet,
+                               int* info) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    factor_final_body(ldp, nparts, info_ws, err, logdet, info);
+}
 
 // ---------------------------------------------------------------------------
 // Selected-inversion kernels
@@ -541,9 +557,8 @@ __global__ void k_factor_final(const double* ldp, int nparts, const int* info_ws
 
 // Phase 1, diagonal tiles: X_J = L_JJ^{-1} ("TRSM(L_ii^T, I)"), stored in the
 // diagonal slots of the workspace; the corner inverse likewise.
-__global__ __launch_bounds__(NT) void k_trtri_all(const double* Lm, double* W, Lay L, int* info) {
-    __shared__ double smem[TRTRI_SMEM_DOUBLES];
-    const int64_t J = blockIdx.x;
+__device__ inline void trtri_body(const double* Lm, double* W, const Lay& L, int* info, int bid, double* smem) {
+    const int64_t J = bid;
     int bad;
     if (J < L.nt) {
         trtri_tile(Lm + L.band(J, 0), L.b, W + L.band(J, 0), L.b, L.b, smem, &bad);
@@ -551,6 +566,10 @@ __global__ __launch_bounds__(NT) void k_trtri_all(const double* Lm, double* W, L
         trtri_tile(Lm + L.corner(), L.ap, W + L.corner(), L.ap, L.ap, smem, &bad);
     }
     if (threadIdx.x == 0 && bad) atomicExch(info, STILES_EBADL);
+}
+__global__ __launch_bounds__(NT) void k_trtri_all(const double* Lm, double* W, Lay L, int* info) {
+    __shared__ double smem[TRTRI_SMEM_DOUBLES];
+    trtri_body(Lm, W, L, info, blockIdx.x, smem);
 }
 
 // Rows of the panel below tile J (band tiles J+1..J+s, then the arrow tile),
@@ -574,13 +593,12 @@ __device__ inline void panel_rows(const Lay& L, double* base, int64_t J, int blk
 
 // Phase 1, off-diagonal tiles: Lhat_{k,J} = L_{k,J} X_J for the band tiles
 // k = J+1..J+s and the arrow tile ("TRMM").  Grid: (J, 64-row block, col block).
-__global__ __launch_bounds__(NT) void k_trmm_all(const double* Lm, double* W, Lay L) {
-    __shared__ double smem[GB_SMEM_DOUBLES];
+__device__ inline void trmm_body(const double* Lm, double* W, const Lay& L, int bid, double* smem) {
     const int nb64 = L.b / 64;
     const int nab = arrow_blocks(L.ap);
     const int rows_max = L.bt * nb64 + nab;
-    const int64_t J = blockIdx.x / (rows_max * nb64);
-    const int r = (int)(blockIdx.x % (rows_max * nb64));
+    const int64_t J = bid / (rows_max * nb64);
+    const int r = (int)(bid % (rows_max * nb64));
     const int blk = r / nb64, cb = r % nb64;
     const int s = L.s(J);
     if (blk >= s * nb64 + nab) return;
@@ -597,17 +615,24 @@ __global__ __launch_bounds__(NT) void k_trmm_all(const double* Lm, double* W, La
              L.b - k0, smem);
     gemm_store(g, smem, 1.0, 0.0, nullptr, 0, Cw + (int64_t)k0 * ld, ld, valid, 64);
 }
+__global__ __launch_bounds__(NT) void k_trmm_all(const double* Lm, double* W, Lay L) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    trmm_body(Lm, W, L, blockIdx.x, smem);
+}
 
 // Phase 2 initial value of each diagonal tile, "LAUUM": Sigma_JJ = X_J^T X_J
 // (and the corner Sigma_AA = X_A^T X_A, which is final).  Lower 64 x 64
 // blocks, mirrored so the tiles are full symmetric.
-__global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, Lay L) {
-    __shared__ double smem[GB_SMEM_DOUBLES];
+__host__ __device__ inline int lauum_per(const Lay& L) {
+    const int nb64 = L.b / 64, nab = arrow_blocks(L.ap);
+    return std::max(nb64 * (nb64 + 1) / 2, nab * (nab + 1) / 2);
+}
+__device__ inline void lauum_body(const double* W, double* S, const Lay& L, int bid, double* smem) {
     const int nb64 = L.b / 64;
     const int nab = arrow_blocks(L.ap);
-    const int per = std::max(nb64 * (nb64 + 1) / 2, nab * (nab + 1) / 2);
-    const int64_t J = blockIdx.x / per;
-    const int t = blockIdx.x % per;
+    const int per = lauum_per(L);
+    const int64_t J = bid / per;
+    const int t = bid % per;
     const double* X;
     double* O;
     int m;
@@ -629,6 +654,10 @@ __global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, La
              m - k0, smem);
     gemm_store_sym(g, smem, 1.0, 0.0, nullptr, 0, O + rb * 64 + (int64_t)cb * 64 * ld,
                    O + cb * 64 + (int64_t)rb * 64 * ld, ld, rb == cb, va, vb);
+}
+__global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, Lay L) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    lauum_body(W, S, L, blockIdx.x, smem);
 }
 
 #define ARW (-1)   // "the arrow" in place of a band tile offset
@@ -695,7 +724,7 @@ __host__ __device__ inline int p2_group_tasks(const Lay& L, int64_t J) {
     return t;
 }
 
-__global__ void k_p2_setup(P2 p, int* ticket, int* err) {
+__device__ inline void p2_setup_body(const P2& p, int* ticket, int* err) {
     const Lay& L = p.L;
     for (int64_t i = threadIdx.x; i < P2_KINDS * L.nt; i += blockDim.x) p.cnt[i] = 0;
     if (threadIdx.x == 0) {
@@ -709,6 +738,7 @@ __global__ void k_p2_setup(P2 p, int* ticket, int* err) {
         *err = 0;
     }
 }
+__global__ void k_p2_setup(P2 p, int* ticket, int* err) { p2_setup_body(p, ticket, err); }
 
 // Operand A = Sigma restricted to a block of rows and a tile of k:
 // rows = block rbl (of rb rows) of tile J+d (d >= 1) or of the arrow (ARW);
@@ -849,9 +879,7 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
     TRACE(t, 6, wall_clock64());
 }
 
-__global__ __launch_bounds__(NT) void k_phase2(P2 p, Sched sc) {
-    __shared__ double smem[P2_SMEM_DOUBLES];
-    __shared__ int sh[2];
+__device__ inline void p2_run(const P2& p, const Sched& sc, double* smem, int* sh) {
     double* red = smem + WS_SMEM_DOUBLES;
     const Lay& L = p.L;
     const int64_t N = L.nt;
@@ -917,15 +945,220 @@ __global__ __launch_bounds__(NT) void k_phase2(P2 p, Sched sc) {
         TRACE(t, 7, (unsigned long long)__smid());
     }
 }
+__global__ __launch_bounds__(NT) void k_phase2(P2 p, Sched sc) {
+    __shared__ double smem[P2_SMEM_DOUBLES];
+    __shared__ int sh[2];
+    p2_run(p, sc, smem, sh);
+}
 
 __global__ void k_selinv_final(const int* info_ws, const int* err, int* info) {
     if (threadIdx.x == 0 && blockIdx.x == 0) *info = (*err != 0) ? *err : *info_ws;
 }
 
 // ---------------------------------------------------------------------------
+// Batched form: many independent matrices per launch
+// ---------------------------------------------------------------------------
+// Every launch of the single-matrix path becomes one launch over all the
+// matrices of a batch that have work in it: a table of segments maps each
+// workgroup to (matrix, workgroup index within that matrix's share), and
+// every matrix keeps its own tickets, counters and workspace, so the tasks,
+// their decomposition and their arithmetic are those of the single-matrix
+// path, matrix by matrix (results are identical bit for bit).
+
+// Sub-buffers of a factor workspace (shared by both forms).
+struct FactorWs {
+    int* winfo;     // first failing column (atomicMin), 0x7fffffff when none
+    int* err;       // scheduler error word
+    double* ldp;    // log det partial pairs, N + 2 of them
+    double* Xc;     // 256 x 256 inverse of the blocked corner
+    double* Yd;     // 16 x 16 diagonal-block inverses of every L_JJ
+    int* cf;        // per tile column counters
+};
+__host__ __device__ inline FactorWs factor_ws(const Lay& L, char* ws) {
+    FactorWs f;
+    f.winfo = (int*)ws;
+    f.err = f.winfo + 16;
+    f.ldp = (double*)(ws + WS_HEAD);
+    f.Xc = f.ldp + 2 * (L.nt + 2);
+    f.Yd = f.Xc + 256 * 256;
+    f.cf = (int*)(f.Yd + L.nt * (int64_t)L.b * 16);
+    return f;
+}
+
+// Sub-buffers of a selinv workspace.
+struct SelinvWs {
+    int* winfo;     // selinv info
+    int* ticket;    // Phase 2 ticket counter
+    int* err;       // Phase 2 scheduler error word
+    double* W;      // Phase 1 tiles (tile layout)
+    int* flags;     // Phase 2 group offsets and ready counters
+};
+__host__ __device__ inline SelinvWs selinv_ws(const Lay& L, char* ws) {
+    SelinvWs v;
+    v.winfo = (int*)ws;
+    v.ticket = v.winfo + 16;
+    v.err = v.winfo + 32;
+    v.W = (double*)(ws + WS_HEAD);
+    v.flags = (int*)(v.W + L.total);
+    return v;
+}
+
+__host__ __device__ inline P2 make_p2(double* S, const SelinvWs& v, const Lay& L, int ntasks) {
+    P2 p;
+    p.S = S;
+    p.W = v.W;
+    p.L = L;
+    p.group_off = v.flags;
+    p.cnt = v.flags + L.nt + 1;
+    p.ntasks = ntasks;
+    return p;
+}
+
+// One matrix of a batch, as the device sees it.
+struct BInst {
+    Lay L;
+    const double* A;
+    double* Lm;
+    double* S;
+    double* logdet;
+    int* info;        // [0] factor, [1] selinv
+    char* ws;         // this matrix's workspace (factor or selinv layout)
+    int p2_tasks;     // Phase 2 task count
+    int nparts;       // log det partial pairs (tile columns + corner blocks)
+};
+// Workgroups [first, next first) of a launch belong to matrix inst; a table
+// of nseg segments ends with a sentinel holding the launch's grid size.
+struct BSeg {
+    int inst;
+    int first;
+};
+struct BArgs {
+    const BInst* bi;
+    const BSeg* seg;
+    int nseg;
+    int64_t spin_limit;
+};
+__device__ inline int bseg_find(const BSeg* seg, int nseg, int b) {
+    int lo = 0, hi = nseg;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (seg[mid].first <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+// this workgroup's matrix, index within the matrix's share, and share size
+#define BATCH_DECODE(a, I, bid, nblk)                                          \
+    const int q_ = bseg_find((a).seg, (a).nseg, (int)blockIdx.x);              \
+    const BInst& I = (a).bi[(a).seg[q_].inst];                                 \
+    const int bid = (int)blockIdx.x - (a).seg[q_].first;                       \
+    const int nblk = (a).seg[q_ + 1].first - (a).seg[q_].first;                \
+    (void)nblk
+
+// Factor set-up of every matrix (one workgroup per matrix): info and error
+// words, tile column counters.
+__global__ __launch_bounds__(NT) void kb_factor_setup(const BInst* bi) {
+    const BInst& I = bi[blockIdx.x];
+    const FactorWs f = factor_ws(I.L, I.ws);
+    if (threadIdx.x == 0) {
+        *f.winfo = 0x7fffffff;
+        *f.err = 0;
+    }
+    const int64_t n = I.L.nt * (int64_t)col_stride(I.L);
+    for (int64_t i = threadIdx.x; i < n; i += NT) f.cf[i] = 0;
+}
+
+__global__ __launch_bounds__(P3_NT) void kb_column(BArgs a, int64_t J) {
+    __shared__ ColSmem sm;
+    __shared__ int sh;
+    BATCH_DECODE(a, I, bid, nblk);
+    const FactorWs f = factor_ws(I.L, I.ws);
+    Sched sc;
+    sc.ticket = nullptr;
+    sc.err = f.err;
+    sc.spin_limit = a.spin_limit;
+    sc.withhold = -1;
+    const int cstride = col_stride(I.L);
+    col_run(sm, sh, I.Lm, I.L, J, f.Yd + J * (int64_t)I.L.b * 16, f.cf + J * cstride, sc, f.ldp + 2 * J, f.winfo);
+}
+
+__global__ __launch_bounds__(NT) void kb_zero_upper(BArgs a) {
+    BATCH_DECODE(a, I, bid, nblk);
+    zero_upper_body(I.Lm, I.L, bid);
+}
+
+// Corner POTRF (a_p <= 256) of the matrices listed in idx, one workgroup each.
+__global__ __launch_bounds__(NT) void kb_corner(const BInst* bi, const int* idx) {
+    extern __shared__ double smem[];
+    const BInst& I = bi[idx[blockIdx.x]];
+    const FactorWs f = factor_ws(I.L, I.ws);
+    potrf_body(I.Lm + I.L.corner(), (int64_t)I.L.ap, I.L.ap, nullptr, 0, f.ldp + 2 * I.L.nt, f.winfo, I.L.nb, smem);
+}
+
+__global__ void kb_factor_final(const BInst* bi) {
+    if (threadIdx.x != 0) return;
+    const BInst& I = bi[blockIdx.x];
+    const FactorWs f = factor_ws(I.L, I.ws);
+    factor_final_body(f.ldp, I.nparts, f.winfo, f.err, I.logdet, I.info);
+}
+
+// Selinv set-up of every matrix (one workgroup per matrix): info word and the
+// Phase 2 ticket, error word, group offsets and counters.
+__global__ __launch_bounds__(NT) void kb_selinv_setup(const BInst* bi) {
+    const BInst& I = bi[blockIdx.x];
+    const SelinvWs v = selinv_ws(I.L, I.ws);
+    if (threadIdx.x == 0) *v.winfo = 0;
+    p2_setup_body(make_p2(I.S, v, I.L, I.p2_tasks), v.ticket, v.err);
+}
+
+__global__ __launch_bounds__(NT) void kb_zero_unused(BArgs a) {
+    BATCH_DECODE(a, I, bid, nblk);
+    zero_unused_body(I.S, I.L, bid, nblk);
+}
+
+__global__ __launch_bounds__(NT) void kb_trtri(BArgs a) {
+    __shared__ double smem[TRTRI_SMEM_DOUBLES];
+    BATCH_DECODE(a, I, bid, nblk);
+    const SelinvWs v = selinv_ws(I.L, I.ws);
+    trtri_body(I.Lm, v.W, I.L, v.winfo, bid, smem);
+}
+
+__global__ __launch_bounds__(NT) void kb_trmm(BArgs a) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    BATCH_DECODE(a, I, bid, nblk);
+    trmm_body(I.Lm, selinv_ws(I.L, I.ws).W, I.L, bid, smem);
+}
+
+__global__ __launch_bounds__(NT) void kb_lauum(BArgs a) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    BATCH_DECODE(a, I, bid, nblk);
+    lauum_body(selinv_ws(I.L, I.ws).W, I.S, I.L, bid, smem);
+}
+
+// Phase 2 of every matrix in one persistent launch: each matrix runs on its
+// own share of the workgroups, with its own tickets.
+__global__ __launch_bounds__(NT) void kb_phase2(BArgs a) {
+    __shared__ double smem[P2_SMEM_DOUBLES];
+    __shared__ int sh[2];
+    BATCH_DECODE(a, I, bid, nblk);
+    const SelinvWs v = selinv_ws(I.L, I.ws);
+    Sched sc;
+    sc.ticket = v.ticket;
+    sc.err = v.err;
+    sc.spin_limit = a.spin_limit;
+    sc.withhold = -1;
+    p2_run(make_p2(I.S, v, I.L, I.p2_tasks), sc, smem, sh);
+}
+
+__global__ void kb_selinv_final(const BInst* bi) {
+    if (threadIdx.x != 0) return;
+    const BInst& I = bi[blockIdx.x];
+    const SelinvWs v = selinv_ws(I.L, I.ws);
+    *(I.info + 1) = (*v.err != 0) ? *v.err : *v.winfo;
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
-#define WS_HEAD 256  // bytes reserved at the start of every workspace (info word)
 
 static inline hipStream_t S_(void* s) { return (hipStream_t)s; }
 
@@ -1036,12 +1269,112 @@ static int grid_for(int64_t work) {
     return (int)g;
 }
 
-// Two internal streams (default priority) and the events of the factor
-// pipeline, one set per device, created on first use: the caller's stream
-// forks into them and joins them back.  Running the chain on an internal
-// stream rather than the caller's keeps the overlap when the caller uses the
-// legacy default stream.  The mutex serialises the enqueue of concurrent
-// factor calls on one device (their kernels may still overlap).
+// log det partial pairs: one per band tile column, one or two for the corner
+static int factor_nparts(const Lay& L) {
+    return (int)L.nt + (L.ap > 0 ? (L.ap <= 256 ? 1 : 2) : 0);
+}
+
+// The corner's Cholesky: one POTRF when a_p <= 256, else POTRF + TRTRI of
+// its first 256 columns, TRSM and SYRK of the rest, POTRF of the remainder.
+static int enqueue_corner(double* Lm, const Lay& L, const FactorWs& f, hipStream_t st) {
+    if (L.ap == 0) return 0;
+    double* Cc = Lm + L.corner();
+    if (L.ap <= 256) {
+        LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), sizeof(double) * potrf_smem_doubles(L.ap), st, Cc,
+               (int64_t)L.ap, L.ap, (double*)nullptr, (int64_t)0, f.ldp + 2 * L.nt, f.winfo, L.nb);
+        return 0;
+    }
+    const int c2 = L.ap - 256;
+    LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), sizeof(double) * potrf_smem_doubles(256), st, Cc,
+           (int64_t)L.ap, 256, f.Xc, (int64_t)256, f.ldp + 2 * L.nt, f.winfo, L.nb);
+    LAUNCH(STILES_TK_OTHER, k_trsm_generic, dim3((c2 + 63) / 64), dim3(NT), 0, st, Cc + 256, (int64_t)L.ap, c2,
+           (const double*)f.Xc, (int64_t)256, 256);
+    const int nab2 = (c2 + 63) / 64;
+    LAUNCH(STILES_TK_OTHER, k_syrk_generic, dim3(nab2 * (nab2 + 1) / 2), dim3(NT), 0, st,
+           Cc + 256 + (int64_t)256 * L.ap, (int64_t)L.ap, (const double*)(Cc + 256), (int64_t)L.ap, c2, 256);
+    LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), sizeof(double) * potrf_smem_doubles(c2), st,
+           Cc + 256 + (int64_t)256 * L.ap, (int64_t)L.ap, c2, (double*)nullptr, (int64_t)0, f.ldp + 2 * (L.nt + 1),
+           f.winfo, L.nb + 256);
+    LAUNCH(STILES_TK_OTHER, k_zero_block, dim3(64), dim3(NT), 0, st, Cc + (int64_t)256 * L.ap, (int64_t)L.ap, 256, c2);
+    return 0;
+}
+
+static int64_t p2_total_tasks(const Lay& L) {
+    int64_t t = 0;
+    for (int64_t J = 0; J < L.nt; ++J) t += p2_group_tasks(L, J);
+    return t;
+}
+
+// Batch plan: layouts, the table area at the start of the workspace (the
+// matrices, then the launch segment tables) and each matrix's workspace.
+static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+struct BPlan {
+    std::vector<stiles_layout> lay;
+    std::vector<size_t> off;   // workspace offset of each matrix
+    size_t table = 0;          // bytes of the table area
+    size_t total = 0;
+    int64_t maxN = 0;
+};
+// factor workspace (FactorWs): head (info, error words) + log det partials
+// (N + 2 pairs) + the 256 x 256 inverse of the blocked corner + the 16 x 16
+// diagonal-block inverses of every L_JJ + the per tile column counters.
+static size_t fws_bytes(const stiles_layout& l) {
+    const Lay L = to_dev(l);
+    return WS_HEAD + sizeof(double) * (size_t)(2 * (l.nt + 2)) +
+           sizeof(double) * (size_t)(256 * 256 + l.nt * (int64_t)l.tile * 16) +
+           sizeof(int) * (size_t)(l.nt * (int64_t)col_stride(L));
+}
+// selinv workspace (SelinvWs): head (info, ticket, error words), the Phase 1
+// tiles (inverted diagonal tiles, Lhat, corner inverse) in the tile layout,
+// then the Phase 2 group offsets (N + 1) and ready counters (P2_KINDS N).
+static size_t sws_bytes(const stiles_layout& l) {
+    return WS_HEAD + sizeof(double) * (size_t)l.total_doubles + sizeof(int) * (size_t)((1 + P2_KINDS) * l.nt + 1);
+}
+static int batch_plan(const stiles_batch_item* items, int count, bool need_sigma, BPlan& pl) {
+    pl.lay.resize(count);
+    pl.off.resize(count);
+    int64_t sumN = 0;
+    for (int k = 0; k < count; ++k) {
+        const stiles_batch_item& it = items[k];
+        if (make_layout(it.n, it.bandwidth, it.arrow, it.tile, &pl.lay[k])) return -1;
+        if (it.reserved != 0 || !it.A || !it.L || !it.logdet || !it.info) return -1;
+        if (need_sigma && (!it.Sigma || it.Sigma == it.L)) return -1;
+        if (need_sigma && p2_total_tasks(to_dev(pl.lay[k])) > 0x7fffffff) return -1;
+        sumN += pl.lay[k].nt;
+        pl.maxN = std::max(pl.maxN, pl.lay[k].nt);
+    }
+    // segment tables: the tile-column launches (sum of N entries plus one
+    // sentinel each), at most six per-matrix launches, and the corner list
+    const size_t nseg = (size_t)sumN + (size_t)pl.maxN + 6 * ((size_t)count + 1);
+    pl.table = align256(sizeof(BInst) * (size_t)count) + align256(sizeof(BSeg) * nseg) +
+               align256(sizeof(int) * (size_t)count);
+    size_t o = pl.table;
+    for (int k = 0; k < count; ++k) {
+        pl.off[k] = o;
+        o += align256(std::max(fws_bytes(pl.lay[k]), sws_bytes(pl.lay[k])));
+    }
+    pl.total = o;
+    return 0;
+}
+
+// Segment table builder: workgroup shares of one launch.
+struct SegTab {
+    std::vector<BSeg> v;
+    size_t begin = 0;
+    int grid = 0;
+    void start(size_t b) { begin = b; grid = 0; }
+    void add(std::vector<BSeg>& all, int inst, int blocks) {
+        if (blocks <= 0) return;
+        all.push_back({inst, grid});
+        grid += blocks;
+    }
+    int finish(std::vector<BSeg>& all) {   // returns the segment count
+        const int n = (int)(all.size() - begin);
+        all.push_back({-1, grid});
+        return n;
+    }
+};
+
 extern "C" {
 
 #ifdef STILES_TASK_TRACE
@@ -1112,26 +1445,9 @@ int stiles_layout_init(int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile
     return make_layout(n, bandwidth, arrow, tile, out);
 }
 
-size_t stiles_factor_workspace_bytes(const stiles_layout* lay) {
-    if (!lay) return 0;
-    // head (info, error words) + log det partials (N + 2 blocks) + the
-    // 256 x 256 inverse of the blocked corner + the 16 x 16 diagonal-block
-    // inverses of every L_JJ + the per tile column counters.
-    const Lay L = to_dev(*lay);
-    return WS_HEAD + sizeof(double) * (size_t)(2 * (lay->nt + 2)) +
-           sizeof(double) * (size_t)(256 * 256 + lay->nt * (int64_t)lay->tile * 16) +
-           sizeof(int) * (size_t)(lay->nt * (int64_t)col_stride(L));
-}
+size_t stiles_factor_workspace_bytes(const stiles_layout* lay) { return lay ? fws_bytes(*lay) : 0; }
 
-// selinv workspace: head (info, ticket, error words), the Phase 1 tiles
-// (inverted diagonal tiles, Lhat, corner inverse) in the tile layout, then
-// the Phase 2 step offsets and ready counters.
-static size_t selinv_flags_ints(const stiles_layout* lay) { return (size_t)(7 * lay->nt + 1); }
-
-size_t stiles_selinv_workspace_bytes(const stiles_layout* lay) {
-    if (!lay) return 0;
-    return WS_HEAD + sizeof(double) * (size_t)lay->total_doubles + sizeof(int) * selinv_flags_ints(lay);
-}
+size_t stiles_selinv_workspace_bytes(const stiles_layout* lay) { return lay ? sws_bytes(*lay) : 0; }
 
 int stiles_pack(const double* ab, const double* arrow_rows, const double* corner, double* tiles,
                 int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile, void* stream) {
@@ -1160,19 +1476,14 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     if (!workspace || workspace_bytes < stiles_factor_workspace_bytes(&lay)) return -9;
     hipStream_t st = S_(stream);
     Lay L = to_dev(lay);
-    char* ws = (char*)workspace;
-    int* winfo = (int*)ws;
-    double* ldp = (double*)(ws + WS_HEAD);
-    double* Xc = ldp + 2 * (L.nt + 2);
-    double* Yd = Xc + 256 * 256;
+    const FactorWs f = factor_ws(L, (char*)workspace);
     const int64_t y_per = (int64_t)L.b * 16;
-    int* cf = (int*)(Yd + L.nt * y_per);
     const int cstride = col_stride(L);
     DevInfo di;
     if (dev_info(&di)) return STILES_EHIP;
     Sched sc;
     sc.ticket = nullptr;
-    sc.err = winfo + 16;
+    sc.err = f.err;
     sc.spin_limit = spin_limit_ticks(di);
     sc.withhold = -1;
 
@@ -1181,9 +1492,9 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
         HIPCHK(hipMemcpyAsync(Lm, A, sizeof(double) * (size_t)L.total, hipMemcpyDeviceToDevice, st));
         tm_end(tm, STILES_TK_OTHER, st);
     }
-    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, winfo, 0x7fffffff);
-    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, sc.err, 0);
-    LAUNCH(STILES_TK_OTHER, k_zero_ints, dim3(grid_for(L.nt * (int64_t)cstride)), dim3(NT), 0, st, cf,
+    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, f.winfo, 0x7fffffff);
+    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, f.err, 0);
+    LAUNCH(STILES_TK_OTHER, k_zero_ints, dim3(grid_for(L.nt * (int64_t)cstride)), dim3(NT), 0, st, f.cf,
            L.nt * (int64_t)cstride);
     // One launch per tile column, in order: POTRF of the diagonal tile, the
     // panel TRSM below it and the trailing updates run as concurrent tasks of
@@ -1191,36 +1502,13 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     for (int64_t J = 0; J < L.nt; ++J) {
         const int ntasks = 1 + col_tr_blocks(L, J) + col_up_blocks(L, J);
         LAUNCH(STILES_TK_FACTOR, k_column, dim3((unsigned)std::min(ntasks, di.cus)), dim3(P3_NT), 0, st, Lm, L, J,
-               Yd + J * y_per, cf + J * cstride, sc, ldp + 2 * J, (int*)winfo);
+               f.Yd + J * y_per, f.cf + J * cstride, sc, f.ldp + 2 * J, f.winfo);
     }
     LAUNCH(STILES_TK_OTHER, k_zero_upper, dim3((unsigned)(8 * L.nt)), dim3(NT), 0, st, Lm, L);
-    int nparts = (int)L.nt;
-    if (L.ap > 0) {
-        double* Cc = Lm + L.corner();
-        if (L.ap <= 256) {
-            LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), sizeof(double) * potrf_smem_doubles(L.ap), st, Cc,
-                               (int64_t)L.ap, L.ap, (double*)nullptr, (int64_t)0, ldp + 2 * L.nt, winfo, L.nb);
-            nparts += 1;
-        } else {
-            const int c2 = L.ap - 256;
-            LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), sizeof(double) * potrf_smem_doubles(256), st, Cc,
-                               (int64_t)L.ap, 256, Xc, (int64_t)256, ldp + 2 * L.nt, winfo, L.nb);
-            LAUNCH(STILES_TK_OTHER, k_trsm_generic, dim3((c2 + 63) / 64), dim3(NT), 0, st, Cc + 256, (int64_t)L.ap, c2,
-                               (const double*)Xc, (int64_t)256, 256);
-            const int nab2 = (c2 + 63) / 64;
-            LAUNCH(STILES_TK_OTHER, k_syrk_generic, dim3(nab2 * (nab2 + 1) / 2), dim3(NT), 0, st,
-                               Cc + 256 + (int64_t)256 * L.ap, (int64_t)L.ap, (const double*)(Cc + 256),
-                               (int64_t)L.ap, c2, 256);
-            LAUNCH(STILES_TK_POTRF, k_potrf, dim3(1), dim3(NT), sizeof(double) * potrf_smem_doubles(c2), st,
-                               Cc + 256 + (int64_t)256 * L.ap, (int64_t)L.ap, c2, (double*)nullptr, (int64_t)0,
-                               ldp + 2 * (L.nt + 1), winfo, L.nb + 256);
-            LAUNCH(STILES_TK_OTHER, k_zero_block, dim3(64), dim3(NT), 0, st, Cc + (int64_t)256 * L.ap, (int64_t)L.ap,
-                               256, c2);
-            nparts += 2;
-        }
-    }
-    LAUNCH(STILES_TK_OTHER, k_factor_final, dim3(1), dim3(64), 0, st, (const double*)ldp, nparts, (const int*)winfo,
-                       (const int*)sc.err, logdet, (int*)info);
+    rc = enqueue_corner(Lm, L, f, st);
+    if (rc) return rc;
+    LAUNCH(STILES_TK_OTHER, k_factor_final, dim3(1), dim3(64), 0, st, (const double*)f.ldp, factor_nparts(L),
+           (const int*)f.winfo, (const int*)f.err, logdet, (int*)info);
     return 0;
 }
 
@@ -1235,55 +1523,238 @@ int stiles_selinv(const double* Lm, double* S, int64_t n, int64_t bandwidth, int
     if (!workspace || workspace_bytes < stiles_selinv_workspace_bytes(&lay)) return -8;
     hipStream_t st = S_(stream);
     Lay L = to_dev(lay);
-    char* ws = (char*)workspace;
-    int* winfo = (int*)ws;
-    double* W = (double*)(ws + WS_HEAD);
+    const SelinvWs v = selinv_ws(L, (char*)workspace);
     const int nb64 = L.b / 64, nab = arrow_blocks(L.ap);
+    const int64_t ntasks = p2_total_tasks(L);
+    if (ntasks > 0x7fffffff) return -3;
 
-    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, winfo, 0);
+    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, v.winfo, 0);
     if (L.bt > 0) {
         const int64_t tail = (int64_t)L.bt * (L.bt + 1) / 2 * L.b * L.b;
         LAUNCH(STILES_TK_OTHER, k_zero_unused, dim3(grid_for(tail)), dim3(NT), 0, st, S, L);
     }
     // Phase 1
-    LAUNCH(STILES_TK_PHASE1, k_trtri_all, dim3((unsigned)(L.nt + (L.ap > 0))), dim3(NT), 0, st, Lm, W, L, winfo);
+    LAUNCH(STILES_TK_PHASE1, k_trtri_all, dim3((unsigned)(L.nt + (L.ap > 0))), dim3(NT), 0, st, Lm, v.W, L, v.winfo);
     {
         const int64_t g = L.nt * (int64_t)(L.bt * nb64 + nab) * nb64;
         if (g > 0) {
-            LAUNCH(STILES_TK_PHASE1, k_trmm_all, dim3((unsigned)g), dim3(NT), 0, st, Lm, W, L);
+            LAUNCH(STILES_TK_PHASE1, k_trmm_all, dim3((unsigned)g), dim3(NT), 0, st, Lm, v.W, L);
         }
     }
     {
-        const int per = std::max(nb64 * (nb64 + 1) / 2, nab * (nab + 1) / 2);
-        const int64_t g = (L.nt + (L.ap > 0)) * (int64_t)per;
-        LAUNCH(STILES_TK_PHASE1, k_lauum_all, dim3((unsigned)g), dim3(NT), 0, st, (const double*)W, S, L);
+        const int64_t g = (L.nt + (L.ap > 0)) * (int64_t)lauum_per(L);
+        LAUNCH(STILES_TK_PHASE1, k_lauum_all, dim3((unsigned)g), dim3(NT), 0, st, (const double*)v.W, S, L);
     }
     // Phase 2, bottom-right to top-left, one persistent launch
     {
         DevInfo di;
         if (dev_info(&di)) return STILES_EHIP;
-        P2 p;
-        p.S = S;
-        p.W = W;
-        p.L = L;
-        int* fl = (int*)(W + L.total);
-        p.group_off = fl;
-        p.cnt = fl + L.nt + 1;
-        int64_t ntasks = 0;
-        for (int64_t J = 0; J < L.nt; ++J) ntasks += p2_group_tasks(L, J);
-        if (ntasks > 0x7fffffff) return -3;
-        p.ntasks = (int)ntasks;
+        const P2 p = make_p2(S, v, L, (int)ntasks);
         Sched sc;
-        sc.ticket = winfo + 16;
-        sc.err = winfo + 32;
+        sc.ticket = v.ticket;
+        sc.err = v.err;
         sc.spin_limit = spin_limit_ticks(di);
         sc.withhold = debug_withhold();
         LAUNCH(STILES_TK_OTHER, k_p2_setup, dim3(1), dim3(NT), 0, st, p, sc.ticket, sc.err);
         const int grid = (int)std::min<int64_t>(ntasks, P2_WG_PER_CU * (int64_t)di.cus);
         LAUNCH(STILES_TK_PHASE2, k_phase2, dim3(grid), dim3(NT), 0, st, p, sc);
     }
-    LAUNCH(STILES_TK_OTHER, k_selinv_final, dim3(1), dim3(64), 0, st, (const int*)winfo, (const int*)(winfo + 32),
+    LAUNCH(STILES_TK_OTHER, k_selinv_final, dim3(1), dim3(64), 0, st, (const int*)v.winfo, (const int*)v.err,
            (int*)info);
+    return 0;
+}
+
+size_t stiles_batch_workspace_bytes(const stiles_batch_item* items, int32_t count) {
+    if (!items || count < 1) return 0;
+    BPlan pl;
+    if (batch_plan(items, count, false, pl)) return 0;
+    return pl.total;
+}
+
+// Host side of both batched calls: the matrix table (and the segment tables
+// appended to `segs`) go to the table area of the workspace in one copy.
+static int batch_upload(const std::vector<BInst>& bi, const std::vector<BSeg>& segs, const std::vector<int>& idx,
+                        char* ws, hipStream_t st) {
+    const size_t o1 = align256(sizeof(BInst) * bi.size()), o2 = o1 + align256(sizeof(BSeg) * segs.size());
+    std::vector<char> h(o2 + sizeof(int) * idx.size());
+    memcpy(h.data(), bi.data(), sizeof(BInst) * bi.size());
+    memcpy(h.data() + o1, segs.data(), sizeof(BSeg) * segs.size());
+    if (!idx.empty()) memcpy(h.data() + o2, idx.data(), sizeof(int) * idx.size());
+    // from pageable memory: the data are staged before the call returns
+    HIPCHK(hipMemcpyAsync(ws, h.data(), h.size(), hipMemcpyHostToDevice, st));
+    return 0;
+}
+
+int stiles_factor_batched(const stiles_batch_item* items, int32_t count, void* workspace, size_t workspace_bytes,
+                          void* stream) {
+    if (!items) return -1;
+    if (count < 1) return -2;
+    BPlan pl;
+    if (batch_plan(items, count, false, pl)) return -1;
+    if (!workspace) return -3;
+    if (workspace_bytes < pl.total) return -4;
+    hipStream_t st = S_(stream);
+    DevInfo di;
+    if (dev_info(&di)) return STILES_EHIP;
+    char* ws = (char*)workspace;
+    std::vector<BInst> bi(count);
+    for (int k = 0; k < count; ++k) {
+        BInst& I = bi[k];
+        memset(&I, 0, sizeof(I));
+        I.L = to_dev(pl.lay[k]);
+        I.A = items[k].A;
+        I.Lm = items[k].L;
+        I.S = items[k].Sigma;
+        I.logdet = items[k].logdet;
+        I.info = items[k].info;
+        I.ws = ws + pl.off[k];
+        I.nparts = factor_nparts(I.L);
+    }
+    const size_t seg0 = align256(sizeof(BInst) * (size_t)count);
+    std::vector<BSeg> segs;
+    std::vector<size_t> col_at(pl.maxN);
+    std::vector<int> col_n(pl.maxN), col_grid(pl.maxN);
+    SegTab t;
+    // tile column J: every matrix with N > J, a share of about one
+    // workgroup per compute unit in all (at least two each; the column's
+    // tasks are dealt out by its own tickets)
+    for (int64_t J = 0; J < pl.maxN; ++J) {
+        int active = 0;
+        for (int k = 0; k < count; ++k) active += bi[k].L.nt > J;
+        const int share = std::max(2, di.cus / std::max(1, active));
+        t.start(segs.size());
+        for (int k = 0; k < count; ++k) {
+            if (bi[k].L.nt <= J) continue;
+            const int ntasks = 1 + col_tr_blocks(bi[k].L, J) + col_up_blocks(bi[k].L, J);
+            t.add(segs, k, std::min(ntasks, share));
+        }
+        col_at[J] = t.begin;
+        col_grid[J] = t.grid;
+        col_n[J] = t.finish(segs);
+    }
+    t.start(segs.size());
+    for (int k = 0; k < count; ++k) t.add(segs, k, (int)(8 * bi[k].L.nt));
+    const size_t zu_at = t.begin;
+    const int zu_grid = t.grid, zu_n = t.finish(segs);
+    std::vector<int> corner;
+    int corner_smem = 0;
+    for (int k = 0; k < count; ++k)
+        if (bi[k].L.ap > 0 && bi[k].L.ap <= 256) {
+            corner.push_back(k);
+            corner_smem = std::max(corner_smem, (int)sizeof(double) * potrf_smem_doubles(bi[k].L.ap));
+        }
+    int rc = batch_upload(bi, segs, corner, ws, st);
+    if (rc) return rc;
+    const BInst* dbi = (const BInst*)ws;
+    const BSeg* dseg = (const BSeg*)(ws + seg0);
+    const int* didx = (const int*)(ws + seg0 + align256(sizeof(BSeg) * segs.size()));
+    const int64_t spin = spin_limit_ticks(di);
+
+    for (int k = 0; k < count; ++k) {
+        if (bi[k].A == bi[k].Lm) continue;
+        hipEvent_t tm = tm_begin(st);
+        HIPCHK(hipMemcpyAsync(bi[k].Lm, bi[k].A, sizeof(double) * (size_t)bi[k].L.total, hipMemcpyDeviceToDevice, st));
+        tm_end(tm, STILES_TK_OTHER, st);
+    }
+    LAUNCH(STILES_TK_OTHER, kb_factor_setup, dim3(count), dim3(NT), 0, st, dbi);
+    for (int64_t J = 0; J < pl.maxN; ++J) {
+        const BArgs a{dbi, dseg + col_at[J], col_n[J], spin};
+        LAUNCH(STILES_TK_FACTOR, kb_column, dim3((unsigned)col_grid[J]), dim3(P3_NT), 0, st, a, J);
+    }
+    {
+        const BArgs a{dbi, dseg + zu_at, zu_n, spin};
+        LAUNCH(STILES_TK_OTHER, kb_zero_upper, dim3((unsigned)zu_grid), dim3(NT), 0, st, a);
+    }
+    if (!corner.empty()) {
+        LAUNCH(STILES_TK_POTRF, kb_corner, dim3((unsigned)corner.size()), dim3(NT), corner_smem, st, dbi, didx);
+    }
+    for (int k = 0; k < count; ++k) {
+        if (bi[k].L.ap <= 256) continue;
+        rc = enqueue_corner(bi[k].Lm, bi[k].L, factor_ws(bi[k].L, bi[k].ws), st);
+        if (rc) return rc;
+    }
+    LAUNCH(STILES_TK_OTHER, kb_factor_final, dim3(count), dim3(64), 0, st, dbi);
+    return 0;
+}
+
+int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* workspace, size_t workspace_bytes,
+                          void* stream) {
+    if (!items) return -1;
+    if (count < 1) return -2;
+    BPlan pl;
+    if (batch_plan(items, count, true, pl)) return -1;
+    if (!workspace) return -3;
+    if (workspace_bytes < pl.total) return -4;
+    hipStream_t st = S_(stream);
+    DevInfo di;
+    if (dev_info(&di)) return STILES_EHIP;
+    char* ws = (char*)workspace;
+    std::vector<BInst> bi(count);
+    int64_t sum_tasks = 0;
+    for (int k = 0; k < count; ++k) {
+        BInst& I = bi[k];
+        memset(&I, 0, sizeof(I));
+        I.L = to_dev(pl.lay[k]);
+        I.A = items[k].A;
+        I.Lm = items[k].L;
+        I.S = items[k].Sigma;
+        I.logdet = items[k].logdet;
+        I.info = items[k].info;
+        I.ws = ws + pl.off[k];
+        I.p2_tasks = (int)p2_total_tasks(I.L);
+        sum_tasks += I.p2_tasks;
+    }
+    const size_t seg0 = align256(sizeof(BInst) * (size_t)count);
+    std::vector<BSeg> segs;
+    SegTab t;
+    struct Launch { size_t at; int n, grid; };
+    auto close = [&](Launch& l) { l.at = t.begin; l.grid = t.grid; l.n = t.finish(segs); };
+    Launch zu, tr, tm, la, p2;
+    t.start(segs.size());
+    for (int k = 0; k < count; ++k) {
+        const Lay& L = bi[k].L;
+        const int64_t tail = (int64_t)L.bt * (L.bt + 1) / 2 * L.b * L.b;
+        if (L.bt > 0) t.add(segs, k, std::min(grid_for(tail), 256));
+    }
+    close(zu);
+    t.start(segs.size());
+    for (int k = 0; k < count; ++k) t.add(segs, k, (int)(bi[k].L.nt + (bi[k].L.ap > 0)));
+    close(tr);
+    t.start(segs.size());
+    for (int k = 0; k < count; ++k) {
+        const Lay& L = bi[k].L;
+        const int nb64 = L.b / 64;
+        t.add(segs, k, (int)(L.nt * (int64_t)(L.bt * nb64 + arrow_blocks(L.ap)) * nb64));
+    }
+    close(tm);
+    t.start(segs.size());
+    for (int k = 0; k < count; ++k) t.add(segs, k, (int)((bi[k].L.nt + (bi[k].L.ap > 0)) * (int64_t)lauum_per(bi[k].L)));
+    close(la);
+    // Phase 2: the resident workgroups shared in proportion to the task
+    // counts, at least one per matrix
+    t.start(segs.size());
+    {
+        const int64_t total = std::min<int64_t>(sum_tasks, P2_WG_PER_CU * (int64_t)di.cus);
+        for (int k = 0; k < count; ++k) {
+            const int64_t want = total * bi[k].p2_tasks / std::max<int64_t>(1, sum_tasks);
+            t.add(segs, k, (int)std::max<int64_t>(1, std::min<int64_t>(bi[k].p2_tasks, want)));
+        }
+    }
+    close(p2);
+    int rc = batch_upload(bi, segs, std::vector<int>(), ws, st);
+    if (rc) return rc;
+    const BInst* dbi = (const BInst*)ws;
+    const BSeg* dseg = (const BSeg*)(ws + seg0);
+    const int64_t spin = spin_limit_ticks(di);
+    auto args = [&](const Launch& l) { return BArgs{dbi, dseg + l.at, l.n, spin}; };
+
+    LAUNCH(STILES_TK_OTHER, kb_selinv_setup, dim3(count), dim3(NT), 0, st, dbi);
+    if (zu.grid > 0) LAUNCH(STILES_TK_OTHER, kb_zero_unused, dim3((unsigned)zu.grid), dim3(NT), 0, st, args(zu));
+    LAUNCH(STILES_TK_PHASE1, kb_trtri, dim3((unsigned)tr.grid), dim3(NT), 0, st, args(tr));
+    if (tm.grid > 0) LAUNCH(STILES_TK_PHASE1, kb_trmm, dim3((unsigned)tm.grid), dim3(NT), 0, st, args(tm));
+    LAUNCH(STILES_TK_PHASE1, kb_lauum, dim3((unsigned)la.grid), dim3(NT), 0, st, args(la));
+    LAUNCH(STILES_TK_PHASE2, kb_phase2, dim3((unsigned)p2.grid), dim3(NT), 0, st, args(p2));
+    LAUNCH(STILES_TK_OTHER, kb_selinv_final, dim3(count), dim3(64), 0, st, dbi);
     return 0;
 }
 

@@ -91,3 +91,23 @@ WORKLOADS = {
     "small": dict(nb=2000, w=32, a=20, tile=64, seed=0),
     "large": dict(nb=100000, w=1024, a=100, tile=256, seed=1),
 }
+
+
+# The batched workload: 64 independent matrices whose band order is uniform
+# on [5,000, 50,000], half-bandwidth drawn from {32, 128, 512} and arrow
+# width uniform on [10, 200]; the shapes come from one seeded stream and
+# matrix k is drawn with seed base + k.
+BATCH = dict(count=64, nb_range=(5000, 50000), widths=(32, 128, 512), a_range=(10, 200), seed=2, base=2000)
+
+
+def batch_shapes(count: int = BATCH["count"], seed: int = BATCH["seed"], nb_range=BATCH["nb_range"],
+                 widths=BATCH["widths"], a_range=BATCH["a_range"]):
+    """[(nb, w, a, seed_k)] of a seeded batch of matrices (see BATCH)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(count):
+        nb = int(rng.integers(nb_range[0], nb_range[1] + 1))
+        w = int(widths[int(rng.integers(0, len(widths)))])
+        a = int(rng.integers(a_range[0], a_range[1] + 1))
+        out.append((nb, w, a, BATCH["base"] + k))
+    return out

@@ -35,6 +35,9 @@ EXPORTED = (
     "stiles_version",
     "stiles_timing_enable",
     "stiles_timing_collect",
+    "stiles_batch_workspace_bytes",
+    "stiles_factor_batched",
+    "stiles_selinv_batched",
 )
 
 TIMING_KINDS = ("potrf", "trsm", "update", "phase1", "phase2", "factor", "other")
@@ -48,6 +51,14 @@ class _CLayout(ctypes.Structure):
         ("arrow_ld", _i32), ("reserved", _i32),
         ("off_band", _i64), ("off_arrow", _i64), ("off_corner", _i64),
         ("total_doubles", _i64),
+    ]
+
+
+class _CBatchItem(ctypes.Structure):
+    _fields_ = [
+        ("n", _i64), ("bandwidth", _i64), ("arrow", _i64),
+        ("tile", _i32), ("reserved", _i32),
+        ("A", _vp), ("L", _vp), ("Sigma", _vp), ("logdet", _vp), ("info", _vp),
     ]
 
 
@@ -89,6 +100,12 @@ def load(path: Optional[str] = None):
     lib.stiles_timing_collect.restype = ctypes.c_int
     lib.stiles_version.argtypes = []
     lib.stiles_version.restype = ctypes.c_int
+    lib.stiles_batch_workspace_bytes.argtypes = [ctypes.POINTER(_CBatchItem), _i32]
+    lib.stiles_batch_workspace_bytes.restype = _sz
+    lib.stiles_factor_batched.argtypes = [ctypes.POINTER(_CBatchItem), _i32, _vp, _sz, _vp]
+    lib.stiles_factor_batched.restype = ctypes.c_int
+    lib.stiles_selinv_batched.argtypes = [ctypes.POINTER(_CBatchItem), _i32, _vp, _sz, _vp]
+    lib.stiles_selinv_batched.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -222,3 +239,77 @@ def timing_collect() -> dict:
     if rc != 0:
         raise StilesError(rc, "stiles_timing_collect")
     return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(TIMING_KINDS)}
+
+
+# ---------------------------------------------------------------------------
+# Batched form (stiles_factor_batched / stiles_selinv_batched)
+# ---------------------------------------------------------------------------
+
+def _batch_items(lays, As=None, Ls=None, Sigmas=None, logdet=None, info=None):
+    items = (_CBatchItem * len(lays))()
+    for k, lay in enumerate(lays):
+        it = items[k]
+        it.n, it.bandwidth, it.arrow, it.tile, it.reserved = lay.n, lay.bandwidth, lay.arrow, lay.tile, 0
+        L = Ls[k] if Ls is not None else None
+        it.A = (As[k] if As is not None else L).data_ptr() if (As is not None or L is not None) else None
+        it.L = L.data_ptr() if L is not None else it.A
+        it.Sigma = Sigmas[k].data_ptr() if Sigmas is not None else None
+        it.logdet = logdet.data_ptr() + 8 * k if logdet is not None else None
+        it.info = info.data_ptr() + 8 * k if info is not None else None
+    return items
+
+
+def batch_workspace_bytes(lays) -> int:
+    """Workspace bytes for a batch of matrices with these layouts (factor and selinv)."""
+    items = (_CBatchItem * len(lays))()
+    for k, lay in enumerate(lays):
+        it = items[k]
+        it.n, it.bandwidth, it.arrow, it.tile, it.reserved = lay.n, lay.bandwidth, lay.arrow, lay.tile, 0
+        it.A = it.L = it.Sigma = it.logdet = it.info = 1   # only the layouts are read
+    nbytes = int(load().stiles_batch_workspace_bytes(items, len(lays)))
+    if nbytes == 0:
+        raise ValueError("invalid batch")
+    return nbytes
+
+
+def factor_batched(As, lays, outs=None, workspace=None, info=None, stream=None):
+    """Cholesky factors of a batch; returns (Ls, logdet[count], info[count, 2]) on the device.
+
+    ``outs[k]`` may be ``As[k]`` (in place).  ``info[:, 0]`` is each matrix's
+    factor info (as :func:`factor`); column 1 is left for :func:`selinv_batched`.
+    """
+    import torch
+    As = [_dev_f64(x, "A") for x in As]
+    dev = As[0].device
+    Ls = outs if outs is not None else [torch.empty_like(x) for x in As]
+    ws = workspace if workspace is not None else torch.empty(batch_workspace_bytes(lays), dtype=torch.uint8,
+                                                             device=dev)
+    logdet = torch.empty(len(As), dtype=torch.float64, device=dev)
+    if info is None:
+        info = torch.zeros((len(As), 2), dtype=torch.int32, device=dev)
+    items = _batch_items(lays, As=As, Ls=Ls, logdet=logdet, info=info)
+    rc = load().stiles_factor_batched(items, len(As), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    if rc != 0:
+        raise StilesError(rc, "stiles_factor_batched")
+    return Ls, logdet, info
+
+
+def selinv_batched(Ls, lays, outs=None, workspace=None, info=None, stream=None):
+    """Sigma on the tile pattern of every L of a batch; returns (Sigmas, info[count, 2]).
+
+    ``info[:, 1]`` receives each matrix's selinv info (as :func:`selinv`).
+    """
+    import torch
+    Ls = [_dev_f64(x, "L") for x in Ls]
+    dev = Ls[0].device
+    Ss = outs if outs is not None else [torch.empty_like(x) for x in Ls]
+    ws = workspace if workspace is not None else torch.empty(batch_workspace_bytes(lays), dtype=torch.uint8,
+                                                             device=dev)
+    if info is None:
+        info = torch.zeros((len(Ls), 2), dtype=torch.int32, device=dev)
+    dummy = torch.empty(len(Ls), dtype=torch.float64, device=dev)
+    items = _batch_items(lays, Ls=Ls, Sigmas=Ss, logdet=dummy, info=info)
+    rc = load().stiles_selinv_batched(items, len(Ls), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    if rc != 0:
+        raise StilesError(rc, "stiles_selinv_batched")
+    return Ss, info

@@ -77,6 +77,47 @@ def test_entry_points_reject_bad_arguments_before_any_gpu_call():
         assert st.strerror(code)
 
 
+def test_batched_entry_points_reject_bad_arguments_before_any_gpu_call():
+    lib = st.load()
+    lays = [st.layout(100, 4, 3, 64), st.layout(700, 130, 0, 128)]
+
+    def items(over=None):
+        it = (st._CBatchItem * 2)()
+        for k, lay in enumerate(lays):
+            c = it[k]
+            c.n, c.bandwidth, c.arrow, c.tile, c.reserved = lay.n, lay.bandwidth, lay.arrow, lay.tile, 0
+            c.A, c.L, c.Sigma, c.logdet, c.info = 8, 16, 24, 32, 40
+        for k, (f, v) in (over or {}).items():
+            setattr(it[k], f, v)
+        return it
+    ws = st.batch_workspace_bytes(lays)
+    need = sum(max(l.factor_workspace_bytes, l.selinv_workspace_bytes) for l in lays)
+    assert ws >= need
+    for fn in (lib.stiles_factor_batched, lib.stiles_selinv_batched):
+        assert fn(None, 2, 8, ws, None) == -1
+        assert fn(items(), 0, 8, ws, None) == -2
+        assert fn(items({1: ("tile", 48)}), 2, 8, ws, None) == -1
+        assert fn(items({0: ("reserved", 1)}), 2, 8, ws, None) == -1
+        assert fn(items({0: ("info", None)}), 2, 8, ws, None) == -1
+        assert fn(items(), 2, None, ws, None) == -3
+        assert fn(items(), 2, 8, ws - 1, None) == -4
+    # the selinv needs Sigma, apart from L; the factor does not read it
+    assert lib.stiles_selinv_batched(items({1: ("Sigma", None)}), 2, 8, ws, None) == -1
+    assert lib.stiles_selinv_batched(items({1: ("Sigma", 16)}), 2, 8, ws, None) == -1
+    assert lib.stiles_factor_batched(items({1: ("Sigma", None)}), 2, 8, ws - 1, None) == -4
+    assert lib.stiles_batch_workspace_bytes(items({1: ("tile", 48)}), 2) == 0
+
+
+def test_batch_shapes_follow_the_stated_distribution():
+    sh = inputs.batch_shapes()
+    assert len(sh) == 64
+    assert sh == inputs.batch_shapes()          # seeded
+    for nb, w, a, seed in sh:
+        assert 5000 <= nb <= 50000 and w in (32, 128, 512) and 10 <= a <= 200
+    assert [s[3] for s in sh] == list(range(2000, 2064))
+    assert {s[1] for s in sh} == {32, 128, 512}
+
+
 @pytest.mark.parametrize("nb,w,a,b", [(200, 20, 7, 64), (60, 10, 5, 64), (300, 299, 0, 64), (130, 0, 17, 128)])
 def test_host_pack_roundtrip(nb, w, a, b):
     M = inputs.arrowhead_spd(nb, w, a, seed=1)
