@@ -26,7 +26,8 @@
 
 struct P3Smem {
     double D[16 * P3_LD];          // diagonal block of the current panel, D(i, j) at D[j * P3_LD + i]
-    double Y[16 * P3_LD];          // Y = L_pp^{-1}, Y(i, j) at Y[i * P3_LD + j]
+    double Y[2][16 * P3_LD];       // Y_p = L_pp^{-1} in Y[p & 1], Y(i, j) at [i * P3_LD + j]: the panel
+                                   // wavefronts still read Y_p while wavefront 0 forms Y_{p+1}
     double S22[8 * 9];             // factor16 scratch: S(i, j) at S22[i * 9 + j]
     double T[8 * 9];               // T = L21 Y11, T(i, j) at T[i * 9 + j]
     double Dn[2][16 * P3_LD];      // next diagonal blocks (by parity), reduced up to two panels back
@@ -109,11 +110,11 @@ __device__ inline void p3_wsync() {
 }
 
 // Store a packed 8 x 8 lower triangle (identical in every lane) into LDS
-// from lane 0, at compile-time addresses.  ToY: into sm.Y ([row][col]) at
+// from lane 0, at compile-time addresses.  ToY: into Y ([row][col]) at
 // block offset o; otherwise into sm.D ([col][row]), the diagonal also into
 // sm.dg.
 template <bool ToY>
-__device__ inline void p3_put8(P3Smem& sm, const double (&l)[36], int o, int base) {
+__device__ inline void p3_put8(P3Smem& sm, double* Y, const double (&l)[36], int o, int base) {
     if ((threadIdx.x & 63) != 0) return;
 #pragma unroll
     for (int jj = 0; jj < 8; ++jj)
@@ -121,7 +122,7 @@ __device__ inline void p3_put8(P3Smem& sm, const double (&l)[36], int o, int bas
         for (int ii = jj; ii < 8; ++ii) {
             const int e = P8(ii, jj);
             if (ToY) {
-                sm.Y[(o + ii) * P3_LD + o + jj] = l[e];
+                Y[(o + ii) * P3_LD + o + jj] = l[e];
             } else {
                 sm.D[(o + jj) * P3_LD + o + ii] = l[e];
                 if (ii == jj) sm.dg[base + o + ii] = l[e];
@@ -131,11 +132,11 @@ __device__ inline void p3_put8(P3Smem& sm, const double (&l)[36], int o, int bas
 
 // Factor the 16 x 16 block in sm.D (lower part) on one wavefront: L_pp back
 // into the lower part of sm.D ([col][row]; the upper part is left as is) and
-// Y = L_pp^{-1} into the lower part of sm.Y ([row][col]; its upper part is
+// Y = L_pp^{-1} into the lower part of Y ([row][col]; its upper part is
 // zero from the start).  With D = [D11 .; D21 D22] (8 x 8 blocks):
 // L11 = chol(D11), L21 = D21 L11^{-T} (row by row), S = D22 - L21 L21^T,
 // L22 = chol(S), and Y = [Y11 0; -Y22 L21 Y11  Y22].
-__device__ inline void p3_factor16(P3Smem& sm, int base, int& fail) {
+__device__ inline void p3_factor16(P3Smem& sm, double* Y, int base, int& fail) {
     const int lane = threadIdx.x & 63;
     double a[36], r[8], l21[8];
     // 1. L11 = chol(D11), in every lane; lane i < 8 forms row i of L21 (in place in sm.D)
@@ -155,9 +156,9 @@ __device__ inline void p3_factor16(P3Smem& sm, int base, int& fail) {
         }
     }
     // 2. Y11 = L11^{-1} (in place); T = L21 Y11 (row i on lane i < 8)
-    p3_put8<false>(sm, a, 0, base);
+    p3_put8<false>(sm, Y, a, 0, base);
     p3_inv8(a, r);
-    p3_put8<true>(sm, a, 0, base);
+    p3_put8<true>(sm, Y, a, 0, base);
     if (lane < 8) {
 #pragma unroll
         for (int j = 0; j < 8; ++j) {
@@ -185,9 +186,9 @@ __device__ inline void p3_factor16(P3Smem& sm, int base, int& fail) {
 #pragma unroll
         for (int i = j; i < 8; ++i) a[P8(i, j)] = sm.S22[i * 9 + j];
     p3_chol8(a, r, base + 8, fail);
-    p3_put8<false>(sm, a, 8, base);
+    p3_put8<false>(sm, Y, a, 8, base);
     p3_inv8(a, r);
-    p3_put8<true>(sm, a, 8, base);
+    p3_put8<true>(sm, Y, a, 8, base);
     // 5. Y21 = -Y22 T, column j on lane j < 8
     if (lane < 8) {
         double t[8];
@@ -198,7 +199,7 @@ __device__ inline void p3_factor16(P3Smem& sm, int base, int& fail) {
             double v = 0.0;
 #pragma unroll
             for (int k = 0; k <= i; ++k) v = fma(a[P8(i, k)], t[k], v);
-            sm.Y[(8 + i) * P3_LD + lane] = -v;
+            Y[(8 + i) * P3_LD + lane] = -v;
         }
     }
 }
@@ -258,13 +259,13 @@ __device__ inline int p3_slot(uint32_t tab, int I, int k) {
 // L_Ip^T = Y C_Ip^T for one tile I > p, in place in the pool (the wavefront
 // reads the whole tile before it writes it) and to global memory
 // (device-coherent stores: a concurrent TRSM reads them).
-__device__ inline void p3_solve_tile(P3Smem& sm, double* Mw, int ldi, uint32_t tab, int I, int p, int lane, int li,
-                                     int lk) {
+__device__ inline void p3_solve_tile(P3Smem& sm, const double* Y, double* Mw, int ldi, uint32_t tab, int I, int p,
+                                     int lane, int li, int lk) {
     double* X = sm.pool[p3_slot(tab, I, p)];
     dbl4 o = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
     for (int r = 0; r < 4; ++r)
-        o = __builtin_amdgcn_mfma_f64_16x16x4f64(sm.Y[li * P3_LD + 4 * r + lk], X[r * 64 + lane], o, 0, 0, 0);
+        o = __builtin_amdgcn_mfma_f64_16x16x4f64(Y[li * P3_LD + 4 * r + lk], X[r * 64 + lane], o, 0, 0, 0);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         st_coh_s(Mw, (uint32_t)((16 * I + li) + (16 * p + 4 * r + lk) * ldi), o[r]);
@@ -283,9 +284,9 @@ __device__ inline void p3_solve_tile(P3Smem& sm, double* Mw, int ldi, uint32_t t
 // basic block; the owner of tile p+2 hands its diagonal block to wavefront 0
 // through Dn.
 template <int S0>
-__device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& sm, const double* Mc, double* Mw,
-                                                int ldi, uint32_t tab, int w, int np, int p, int lane, int li,
-                                                int lk) {
+__device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& sm, const double* Y, const double* Mc,
+                                                double* Mw, int ldi, uint32_t tab, int w, int np, int p, int lane,
+                                                int li, int lk) {
     constexpr int NS = P3_SLOTS - S0;
     const int c2 = 16 * (p + 2);
     const int lo = lk * 16 + li;
@@ -303,7 +304,7 @@ __device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& s
         }
         double yv[4];
 #pragma unroll
-        for (int r = 0; r < 4; ++r) yv[r] = sm.Y[li * P3_LD + 4 * r + lk];
+        for (int r = 0; r < 4; ++r) yv[r] = Y[li * P3_LD + 4 * r + lk];
 #pragma unroll
         for (int r = 0; r < 4; ++r)
 #pragma unroll
@@ -395,14 +396,14 @@ __device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& s
 
 // p3_update_slots<s0> for a run-time s0 < P3_SLOTS.
 template <int S0 = 0>
-__device__ __forceinline__ void p3_update_dispatch(int s0, dbl4 (&nxt)[P3_SLOTS], P3Smem& sm, const double* Mc,
-                                                   double* Mw, int ldi, uint32_t tab, int w, int np, int p, int lane,
-                                                   int li, int lk) {
+__device__ __forceinline__ void p3_update_dispatch(int s0, dbl4 (&nxt)[P3_SLOTS], P3Smem& sm, const double* Y,
+                                                   const double* Mc, double* Mw, int ldi, uint32_t tab, int w, int np,
+                                                   int p, int lane, int li, int lk) {
     if constexpr (S0 == P3_SLOTS - 1) {
-        p3_update_slots<S0>(nxt, sm, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
+        p3_update_slots<S0>(nxt, sm, Y, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
     } else {
-        if (s0 == S0) p3_update_slots<S0>(nxt, sm, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
-        else p3_update_dispatch<S0 + 1>(s0, nxt, sm, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
+        if (s0 == S0) p3_update_slots<S0>(nxt, sm, Y, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
+        else p3_update_dispatch<S0 + 1>(s0, nxt, sm, Y, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
     }
 }
 
@@ -432,7 +433,9 @@ __device__ __forceinline__ void p3_update_dispatch(int s0, dbl4 (&nxt)[P3_SLOTS]
 //         p+1 (into the pool, solved from S(p+1) on) and reduce the tiles of
 //         panel p+2 over panels 0..p; the
 //         owner of tile p+2 hands its diagonal block to wavefront 0 through Dn
-//         (by parity).
+//         (by parity).  Y_p and Y_{p+1} live in two LDS buffers (by parity):
+//         the panel wavefronts' solves of panel p in U(p) still read Y_p while
+//         wavefront 0 writes Y_{p+1}.
 // Every tile of L stays in the LDS pool from its reduction to its last use,
 // so global memory is read only for the raw tiles, each once.  The chain of
 // diagonal factorizations overlaps all the other work.
@@ -463,7 +466,7 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
         const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
         sm.D[j * P3_LD + i] = ld_s(Mc, (uint32_t)(i + j * ldi));
     }
-    for (int e = threadIdx.x; e < 16 * P3_LD; e += 256) sm.Y[e] = 0.0;
+    for (int e = threadIdx.x; e < 2 * 16 * P3_LD; e += 256) sm.Y[0][e] = 0.0;
     // panel wavefronts w = 1..P3_PW own the row tiles I = P3_PW s + w >= 1 of every panel
     dbl4 nxt[P3_SLOTS];
     // raw tiles of panel 1 (nothing to reduce yet); tile 1 is owned by
@@ -481,7 +484,7 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
         }
     }
     __syncthreads();
-    if (w == 0) p3_factor16(sm, 0, fail);
+    if (w == 0) p3_factor16(sm, sm.Y[0], 0, fail);
     p3_bar_lds();
     for (int p = 0; p < np; ++p) {
         const int c0 = 16 * p;
@@ -493,7 +496,7 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
             for (int q = 0; q < 4; ++q) {
                 const int i = lane & 15, j = (lane >> 4) + 4 * q;
                 dv[q] = (j <= i) ? sm.D[j * P3_LD + i] : 0.0;
-                yv[q] = sm.Y[i * P3_LD + j];
+                yv[q] = sm.Y[p & 1][i * P3_LD + j];
             }
 #pragma unroll
             for (int q = 0; q < 4; ++q) {
@@ -504,8 +507,9 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
         } else {
             // the tiles other wavefronts read in U(p): (p+1, p) and (p+2, p)
             // (each owned by a different wavefront); the rest waits for U(p)
-            if (p + 1 < np && ((p + 1) - w) % P3_PW == 0) p3_solve_tile(sm, Mw, ldi, tab, p + 1, p, lane, li, lk);
-            if (p + 2 < np && ((p + 2) - w) % P3_PW == 0) p3_solve_tile(sm, Mw, ldi, tab, p + 2, p, lane, li, lk);
+            const double* Yp = sm.Y[p & 1];
+            if (p + 1 < np && ((p + 1) - w) % P3_PW == 0) p3_solve_tile(sm, Yp, Mw, ldi, tab, p + 1, p, lane, li, lk);
+            if (p + 2 < np && ((p + 2) - w) % P3_PW == 0) p3_solve_tile(sm, Yp, Mw, ldi, tab, p + 2, p, lane, li, lk);
         }
         p3_bar_lds();   // panel p of L in the pool (the global stores stay in flight)
         if (p + 1 == np) break;
@@ -524,11 +528,11 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
 #pragma unroll
             for (int r = 0; r < 4; ++r) sm.D[(4 * r + lk) * P3_LD + li] = acc[r];
             p3_wsync();
-            p3_factor16(sm, c0 + 16, fail);
+            p3_factor16(sm, sm.Y[(p + 1) & 1], c0 + 16, fail);
         } else if (p + 2 < np) {
             // slots s >= s0 hold the tiles I >= p+2
             const int s0 = imin_(P3_SLOTS - 1, imax_(0, (p + 2 - w + P3_PW - 1) / P3_PW));
-            p3_update_dispatch(s0, nxt, sm, Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
+            p3_update_dispatch(s0, nxt, sm, sm.Y[p & 1], Mc, Mw, ldi, tab, w, np, p, lane, li, lk);
         }
         // D, Y of p+1; panel p+1 in the pool; Dn; and the stores of panel p
         // complete, so it is announced.

@@ -473,18 +473,14 @@ union ColSmem {
     P3Smem po;
     TrSmem tr;
 };
-__device__ inline void col_run(ColSmem& sm, int& sh, double* Lm, const Lay& L, int64_t J, double* Yd, int* cf,
-                               const Sched& sc, double* ldp, int* info) {
+// Task t of tile column J; false when the kernel must stop (a wait failed).
+__device__ inline bool col_task(ColSmem& sm, int& sh, double* Lm, const Lay& L, int64_t J, double* Yd, int* cf,
+                                const Sched& st, double* ldp, int* info, int t) {
     const int ntr = col_tr_blocks(L, J);
-    const int ntasks = 1 + ntr + col_up_blocks(L, J);
     const int nbr = L.b / 16, s = L.s(J);
     int* fpo = cf + CF_PO;
     int* ftr = cf + CF_TR;
-    Sched st = sc;
-    st.ticket = cf + CF_TICKET;
-    for (;;) {
-        const int t = sched_next(st, ntasks, &sh);
-        if (t < 0) return;
+    {
         if (t == 0) {
             int fail;
             double ls, lc;
@@ -500,11 +496,23 @@ __device__ inline void col_run(ColSmem& sm, int& sh, double* Lm, const Lay& L, i
             int ld;
             if (g < s * nbr) { C = Lm + L.band(J, 1 + g / nbr) + (g % nbr) * 16; ld = L.b; }
             else { C = Lm + L.arrow(J) + (g - s * nbr) * 16; ld = L.ap; }
-            if (!tr_panel(C, ld, Lm + L.band(J, 0), Yd, L.b, fpo, ftr + g, st, sm.tr)) return;
+            if (!tr_panel(C, ld, Lm + L.band(J, 0), Yd, L.b, fpo, ftr + g, st, sm.tr)) return false;
         } else {
             const UpBlock u = col_up_decode(Lm, L, J, t - 1 - ntr);
-            if (!col_update(u, ftr, L.b / 16, st, &sh)) return;
+            if (!col_update(u, ftr, L.b / 16, st, &sh)) return false;
         }
+    }
+    return true;
+}
+__device__ inline void col_run(ColSmem& sm, int& sh, double* Lm, const Lay& L, int64_t J, double* Yd, int* cf,
+                               const Sched& sc, double* ldp, int* info) {
+    const int ntasks = 1 + col_tr_blocks(L, J) + col_up_blocks(L, J);
+    Sched st = sc;
+    st.ticket = cf + CF_TICKET;
+    for (;;) {
+        const int t = sched_next(st, ntasks, &sh);
+        if (t < 0) return;
+        if (!col_task(sm, sh, Lm, L, J, Yd, cf, st, ldp, info, t)) return;
     }
 }
 __global__ __launch_bounds__(P3_NT) void k_column(double* Lm, Lay L, int64_t J, double* Yd, int* cf, Sched sc,
@@ -1067,18 +1075,45 @@ __global__ __launch_bounds__(NT) void kb_factor_setup(const BInst* bi) {
     for (int64_t i = threadIdx.x; i < n; i += NT) f.cf[i] = 0;
 }
 
-__global__ __launch_bounds__(P3_NT) void kb_column(BArgs a, int64_t J) {
+// Tile column J of every matrix with N > J in one launch, all its tasks on
+// one ticket queue: ticket g is local task t of matrix order[g - off[t]]
+// (the matrices sorted by decreasing task count, so those with more than t
+// tasks come first), i.e. task 0 (the POTRFs) of every matrix first, then
+// task 1 of every matrix, and so on.  Each matrix's tasks keep their order, so
+// every task waits only for smaller tickets.
+struct BColArgs {
+    const BInst* bi;
+    const int* off;      // [T + 1], off[T] = ntot
+    const int* order;
+    int T;
+    int ntot;
+    int* ticket;
+    int* err;            // the batch's error word
+    int64_t spin_limit;
+};
+__global__ __launch_bounds__(P3_NT) void kb_column(BColArgs a, int64_t J) {
     __shared__ ColSmem sm;
     __shared__ int sh;
-    BATCH_DECODE(a, I, bid, nblk);
-    const FactorWs f = factor_ws(I.L, I.ws);
     Sched sc;
-    sc.ticket = nullptr;
-    sc.err = f.err;
+    sc.ticket = a.ticket;
+    sc.err = a.err;
     sc.spin_limit = a.spin_limit;
     sc.withhold = -1;
-    const int cstride = col_stride(I.L);
-    col_run(sm, sh, I.Lm, I.L, J, f.Yd + J * (int64_t)I.L.b * 16, f.cf + J * cstride, sc, f.ldp + 2 * J, f.winfo);
+    for (;;) {
+        const int g = sched_next(sc, a.ntot, &sh);
+        if (g < 0) return;
+        int lo = 0, hi = a.T;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (a.off[mid] <= g) lo = mid; else hi = mid;
+        }
+        const int t = lo;
+        const BInst& I = a.bi[a.order[g - a.off[t]]];
+        const FactorWs f = factor_ws(I.L, I.ws);
+        if (!col_task(sm, sh, I.Lm, I.L, J, f.Yd + J * (int64_t)I.L.b * 16, f.cf + J * col_stride(I.L), sc,
+                      f.ldp + 2 * J, f.winfo, t))
+            return;
+    }
 }
 
 __global__ __launch_bounds__(NT) void kb_zero_upper(BArgs a) {
@@ -1094,11 +1129,11 @@ __global__ __launch_bounds__(NT) void kb_corner(const BInst* bi, const int* idx)
     potrf_body(I.Lm + I.L.corner(), (int64_t)I.L.ap, I.L.ap, nullptr, 0, f.ldp + 2 * I.L.nt, f.winfo, I.L.nb, smem);
 }
 
-__global__ void kb_factor_final(const BInst* bi) {
+__global__ void kb_factor_final(const BInst* bi, const int* err) {
     if (threadIdx.x != 0) return;
     const BInst& I = bi[blockIdx.x];
     const FactorWs f = factor_ws(I.L, I.ws);
-    factor_final_body(f.ldp, I.nparts, f.winfo, f.err, I.logdet, I.info);
+    factor_final_body(f.ldp, I.nparts, f.winfo, err, I.logdet, I.info);
 }
 
 // Selinv set-up of every matrix (one workgroup per matrix): info word and the
@@ -1343,11 +1378,18 @@ static int batch_plan(const stiles_batch_item* items, int count, bool need_sigma
         sumN += pl.lay[k].nt;
         pl.maxN = std::max(pl.maxN, pl.lay[k].nt);
     }
-    // segment tables: the tile-column launches (sum of N entries plus one
-    // sentinel each), at most six per-matrix launches, and the corner list
-    const size_t nseg = (size_t)sumN + (size_t)pl.maxN + 6 * ((size_t)count + 1);
-    pl.table = align256(sizeof(BInst) * (size_t)count) + align256(sizeof(BSeg) * nseg) +
-               align256(sizeof(int) * (size_t)count);
+    // segment tables of at most six per-matrix launches; ints: the corner
+    // list, the error word and a ticket per tile column, and the queue tables
+    // of the tile-column launches (off: at most tmax + 1 per column; order:
+    // sum of N)
+    int64_t tmax = 0;
+    for (int k = 0; k < count; ++k) {
+        const Lay L = to_dev(pl.lay[k]);
+        tmax = std::max<int64_t>(tmax, 1 + col_tr_blocks(L, 0) + col_up_blocks(L, 0));
+    }
+    const size_t nseg = 6 * ((size_t)count + 1);
+    const size_t nint = (size_t)count + 1 + (size_t)pl.maxN + (size_t)pl.maxN * (size_t)(tmax + 1) + (size_t)sumN;
+    pl.table = align256(sizeof(BInst) * (size_t)count) + align256(sizeof(BSeg) * nseg) + align256(sizeof(int) * nint);
     size_t o = pl.table;
     for (int k = 0; k < count; ++k) {
         pl.off[k] = o;
@@ -1575,7 +1617,7 @@ size_t stiles_batch_workspace_bytes(const stiles_batch_item* items, int32_t coun
 // appended to `segs`) go to the table area of the workspace in one copy.
 static int batch_upload(const std::vector<BInst>& bi, const std::vector<BSeg>& segs, const std::vector<int>& idx,
                         char* ws, hipStream_t st) {
-    const size_t o1 = align256(sizeof(BInst) * bi.size()), o2 = o1 + align256(sizeof(BSeg) * segs.size());
+    const size_t o1 = align256(sizeof(BInst) * bi.size()), o2 = o1 + align256(sizeof(BSeg) * 6 * (bi.size() + 1));
     std::vector<char> h(o2 + sizeof(int) * idx.size());
     memcpy(h.data(), bi.data(), sizeof(BInst) * bi.size());
     memcpy(h.data() + o1, segs.data(), sizeof(BSeg) * segs.size());
@@ -1611,43 +1653,50 @@ int stiles_factor_batched(const stiles_batch_item* items, int32_t count, void* w
         I.nparts = factor_nparts(I.L);
     }
     const size_t seg0 = align256(sizeof(BInst) * (size_t)count);
+    const size_t int0 = seg0 + align256(sizeof(BSeg) * 6 * ((size_t)count + 1));
     std::vector<BSeg> segs;
-    std::vector<size_t> col_at(pl.maxN);
-    std::vector<int> col_n(pl.maxN), col_grid(pl.maxN);
     SegTab t;
-    // tile column J: every matrix with N > J, a share of about one
-    // workgroup per compute unit in all (at least two each; the column's
-    // tasks are dealt out by its own tickets)
-    for (int64_t J = 0; J < pl.maxN; ++J) {
-        int active = 0;
-        for (int k = 0; k < count; ++k) active += bi[k].L.nt > J;
-        const int share = std::max(2, di.cus / std::max(1, active));
-        t.start(segs.size());
-        for (int k = 0; k < count; ++k) {
-            if (bi[k].L.nt <= J) continue;
-            const int ntasks = 1 + col_tr_blocks(bi[k].L, J) + col_up_blocks(bi[k].L, J);
-            t.add(segs, k, std::min(ntasks, share));
-        }
-        col_at[J] = t.begin;
-        col_grid[J] = t.grid;
-        col_n[J] = t.finish(segs);
-    }
     t.start(segs.size());
     for (int k = 0; k < count; ++k) t.add(segs, k, (int)(8 * bi[k].L.nt));
     const size_t zu_at = t.begin;
     const int zu_grid = t.grid, zu_n = t.finish(segs);
-    std::vector<int> corner;
-    int corner_smem = 0;
+    // ints: [0, count) corner list, [count] error word, then one ticket per
+    // tile column (zero as uploaded), then the queue tables
+    std::vector<int> ints((size_t)count + 1 + (size_t)pl.maxN, 0);
+    int ncorner = 0, corner_smem = 0;
     for (int k = 0; k < count; ++k)
         if (bi[k].L.ap > 0 && bi[k].L.ap <= 256) {
-            corner.push_back(k);
+            ints[ncorner++] = k;
             corner_smem = std::max(corner_smem, (int)sizeof(double) * potrf_smem_doubles(bi[k].L.ap));
         }
-    int rc = batch_upload(bi, segs, corner, ws, st);
+    const size_t err_at = (size_t)count, tick_at = (size_t)count + 1;
+    struct ColQ { size_t off_at, order_at; int T, ntot; };
+    std::vector<ColQ> cq(pl.maxN);
+    std::vector<std::pair<int, int>> nt_k;
+    for (int64_t J = 0; J < pl.maxN; ++J) {
+        nt_k.clear();
+        for (int k = 0; k < count; ++k)
+            if (bi[k].L.nt > J) nt_k.push_back({1 + col_tr_blocks(bi[k].L, J) + col_up_blocks(bi[k].L, J), k});
+        std::stable_sort(nt_k.begin(), nt_k.end(), [](const std::pair<int, int>& x, const std::pair<int, int>& y) {
+            return x.first > y.first;
+        });
+        ColQ& q = cq[J];
+        q.T = nt_k.empty() ? 0 : nt_k.front().first;
+        q.off_at = ints.size();
+        int acc = 0;
+        for (int tt = 0; tt <= q.T; ++tt) {
+            ints.push_back(acc);
+            for (const auto& e : nt_k) acc += e.first > tt;
+        }
+        q.ntot = acc;
+        q.order_at = ints.size();
+        for (const auto& e : nt_k) ints.push_back(e.second);
+    }
+    int rc = batch_upload(bi, segs, ints, ws, st);
     if (rc) return rc;
     const BInst* dbi = (const BInst*)ws;
     const BSeg* dseg = (const BSeg*)(ws + seg0);
-    const int* didx = (const int*)(ws + seg0 + align256(sizeof(BSeg) * segs.size()));
+    int* dint = (int*)(ws + int0);
     const int64_t spin = spin_limit_ticks(di);
 
     for (int k = 0; k < count; ++k) {
@@ -1658,22 +1707,23 @@ int stiles_factor_batched(const stiles_batch_item* items, int32_t count, void* w
     }
     LAUNCH(STILES_TK_OTHER, kb_factor_setup, dim3(count), dim3(NT), 0, st, dbi);
     for (int64_t J = 0; J < pl.maxN; ++J) {
-        const BArgs a{dbi, dseg + col_at[J], col_n[J], spin};
-        LAUNCH(STILES_TK_FACTOR, kb_column, dim3((unsigned)col_grid[J]), dim3(P3_NT), 0, st, a, J);
+        const ColQ& q = cq[J];
+        const BColArgs a{dbi, dint + q.off_at, dint + q.order_at, q.T, q.ntot, dint + tick_at + J, dint + err_at, spin};
+        LAUNCH(STILES_TK_FACTOR, kb_column, dim3((unsigned)std::min(q.ntot, di.cus)), dim3(P3_NT), 0, st, a, J);
     }
     {
         const BArgs a{dbi, dseg + zu_at, zu_n, spin};
         LAUNCH(STILES_TK_OTHER, kb_zero_upper, dim3((unsigned)zu_grid), dim3(NT), 0, st, a);
     }
-    if (!corner.empty()) {
-        LAUNCH(STILES_TK_POTRF, kb_corner, dim3((unsigned)corner.size()), dim3(NT), corner_smem, st, dbi, didx);
+    if (ncorner > 0) {
+        LAUNCH(STILES_TK_POTRF, kb_corner, dim3((unsigned)ncorner), dim3(NT), corner_smem, st, dbi, (const int*)dint);
     }
     for (int k = 0; k < count; ++k) {
         if (bi[k].L.ap <= 256) continue;
         rc = enqueue_corner(bi[k].Lm, bi[k].L, factor_ws(bi[k].L, bi[k].ws), st);
         if (rc) return rc;
     }
-    LAUNCH(STILES_TK_OTHER, kb_factor_final, dim3(count), dim3(64), 0, st, dbi);
+    LAUNCH(STILES_TK_OTHER, kb_factor_final, dim3(count), dim3(64), 0, st, dbi, (const int*)(dint + err_at));
     return 0;
 }
 

@@ -144,3 +144,16 @@ def test_workspace_reused_by_a_smaller_batch(torch_cuda):
         for k in range(len(As)):
             assert torch.equal(Ls[k], plain[k][0]) and torch.equal(Ss[k], plain[k][1])
             assert float(ld[k].item()) == float(plain[k][2].item())
+
+
+def test_batched_repeatable(mix_run, torch_cuda):
+    """The mixed batch again, three times: bit for bit the first result each
+    time (the batch puts the diagonal-tile factorizations under the heaviest
+    concurrent load, where an ordering fault would show)."""
+    torch = torch_cuda
+    r = mix_run
+    for rep in range(3):
+        Ls, Ss, ld, info = _batched(r["As"], r["lays"])
+        torch.cuda.synchronize()
+        for k in range(len(MIX)):
+            assert torch.equal(Ls[k], r["Ls"][k]) and torch.equal(Ss[k], r["Ss"][k]), (rep, k)
