@@ -85,6 +85,7 @@ def cpu_baseline(w, a, b, nb_sample, seed):
 WORKLOADS = {
     "large": dict(nb=100000, w=1024, a=100, b=256, seed=1, cpu_nb=100000),
     "small": dict(nb=2000, w=32, a=20, b=64, seed=0, cpu_nb=2000),
+    "batched": dict(),
 }
 WORK = WORKLOADS["large"]
 
@@ -97,11 +98,17 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--tile", type=int, default=0, help="batched: this tile size instead of the autotuner's")
+    ap.add_argument("--no-plain", action="store_true",
+                    help="batched: skip the plain-form timing and the per-matrix comparison (profiling runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
               "(the batched/served forms shard by instance, see the design notes)", file=sys.stderr)
         return 2
+
+    if args.workload == "batched":
+        return main_batched(args)
 
     import numpy as np
     import torch
@@ -209,6 +216,115 @@ def main() -> int:
         "roofline": roofline,
         "cpu_baseline": cpu,
         "kernels": breakdown,
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
+def main_batched(args) -> int:
+    """64 uneven matrices (inputs.BATCH): the tile size picked by the
+    autotuner, then K timed passes of pack + batched factor + batched selinv,
+    against the plain form (each matrix alone, its own launches) on the same
+    matrices, at the batch's tile size and at each matrix's fastest one."""
+    import numpy as np
+    import torch
+    from paper_2504_19171_amd import autotune
+    from paper_2504_19171_amd import flops as fl
+    from paper_2504_19171_amd import inputs
+    from paper_2504_19171_amd import stiles as st
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    shapes = inputs.batch_shapes()
+    mats, nws = [], []
+    for nb, w, a, seed in shapes:
+        M = inputs.arrowhead_spd(nb, w, a, seed=seed)
+        mats.append((torch.from_numpy(M.ab).to(dev), torch.from_numpy(M.P).to(dev) if a else None,
+                     torch.from_numpy(M.C).to(dev) if a else None))
+        nws.append((M.n, w, a))
+    torch.cuda.synchronize()
+    print(f"bench: {len(shapes)} matrices ready in {time.perf_counter() - t0:.1f} s "
+          f"(n {min(s[0] for s in shapes)}..{max(s[0] for s in shapes)}, w in {{32, 128, 512}})",
+          file=sys.stderr, flush=True)
+
+    if args.tile:
+        tile, tune_ms = args.tile, None
+    else:
+        tile, tune_ms = autotune.tune_batch(mats, nws)
+        print(f"bench: autotuner ms per batched pass {tune_ms} -> tile {tile}", file=sys.stderr, flush=True)
+    plain_same = plain_best = None
+    if not args.no_plain:
+        plain = {b: autotune.time_plain(mats, nws, b) for b in autotune.CANDIDATES}
+        plain_same = sum(plain[tile]) if tile in plain else sum(autotune.time_plain(mats, nws, tile))
+        plain_best = sum(min(plain[b][k] for b in plain) for k in range(len(shapes)))
+        print(f"bench: plain ms per pass {[(b, round(sum(v), 1)) for b, v in plain.items()]}", file=sys.stderr,
+              flush=True)
+
+    _, buf = autotune.time_batched(mats, nws, tile)
+    for i in range(args.warmup):
+        autotune.run_batched(buf)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    st.timing_enable(True)
+    ev[0].record(stream)
+    for i in range(args.steps):
+        ld, info = autotune.run_batched(buf)
+        ev[i + 1].record(stream)
+    torch.cuda.synchronize()
+    per_kind = st.timing_collect()
+    st.timing_enable(False)
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
+    total_ms = ev[0].elapsed_time(ev[-1])
+    ms_step = total_ms / args.steps
+
+    # every matrix: batched result == single-matrix result, bit for bit
+    same = None if args.no_plain else True
+    for k, ((ab, P, C), lay) in enumerate(zip(mats, buf["lays"]) if not args.no_plain else []):
+        A = st.pack(ab, P, C, lay)
+        L, ld1, _ = st.factor(A, lay)
+        S, _ = st.selinv(L, lay)
+        same &= bool(torch.equal(L, buf["Ls"][k]) and torch.equal(S, buf["Ss"][k]))
+        same &= float(ld1.item()) == float(ld[k].item())
+        del A, L, S
+    ok = bool((info.cpu().numpy() == 0).all()) and bool(torch.isfinite(ld).all()) and same is not False
+
+    flop = sum(fl.factor_flops(n - a, w, a, tile) + fl.selinv_flops(n - a, w, a, tile) for (n, w, a) in nws)
+    value = flop / (ms_step / 1e3) / 1e9
+    srt = sorted(step_ms)
+    kinds = {k: {"ms_per_step": round(v[0] / args.steps, 3), "launches_per_step": v[1] // max(args.steps, 1)}
+             for k, v in per_kind.items() if v[1]}
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {len(shapes)} matrices, band order uniform on [5,000, 50,000], "
+                               "half-bandwidth in {32, 128, 512}, arrow uniform on [10, 200], seeded N(0,1) "
+                               "band and arrow, diagonal = row |sum| + 1",
+                   "instances": len(shapes), "tile": tile, "autotune_ms": tune_ms,
+                   "step": "pack + batched factor (L, log det) + batched selinv, all matrices",
+                   "flops_per_step": flop},
+        "solves_per_s": round(len(shapes) * 1e3 / ms_step, 3),
+        "plain": None if plain_same is None else {
+            "ms_same_tile": round(plain_same, 3), "ms_best_tile_each": round(plain_best, 3),
+            "solves_per_s_same_tile": round(len(shapes) * 1e3 / plain_same, 3),
+            "solves_per_s_best_tile_each": round(len(shapes) * 1e3 / plain_best, 3)},
+        "speedup_vs_plain": None if plain_same is None else {
+            "same_tile": round(plain_same / ms_step, 2), "best_tile_each": round(plain_best / ms_step, 2)},
+        "latency_ms_p50": round(srt[len(srt) // 2], 4),
+        "latency_ms_p99": round(srt[min(len(srt) - 1, int(0.99 * len(srt)))], 4),
+        "ok": ok,
+        "bitwise_equal_to_single": same,
+        "kernels": kinds,
     }
     print(json.dumps(out), flush=True)
     return 0 if ok else 1

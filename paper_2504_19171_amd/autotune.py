@@ -1,0 +1,101 @@
+"""Tile-size autotuner: the tile size b is picked by timing, on the device,
+the factorization and selected inversion of the actual matrices with each
+candidate b (no model of the cost).
+
+The tile size is a free parameter of the method (the paper tunes it per
+platform, Sec. IV-D); for a batch the tile-column launches run in step
+across the matrices, so one b serves the whole batch.  Every timed run is the
+library's own HIP path; the candidates' buffers are released between runs.
+"""
+from __future__ import annotations
+
+from typing import Dict, List, Sequence, Tuple
+
+from . import stiles as st
+
+CANDIDATES = (64, 128, 256)
+
+
+def _events():
+    import torch
+    return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+
+def batch_buffers(mats, shapes, tile):
+    """Layouts, packed inputs and output buffers of a batch at one tile size.
+
+    mats: [(ab, P, C)] device tensors (canonical band form, P and C None
+    without an arrow); shapes: [(n, w, a)]."""
+    import torch
+    lays = [st.layout(n, w, a, tile) for (n, w, a) in shapes]
+    As = [st.pack(ab, P, C, lay) for (ab, P, C), lay in zip(mats, lays)]
+    dev = As[0].device
+    Ls = [torch.empty_like(x) for x in As]
+    Ss = [torch.empty_like(x) for x in As]
+    ws = torch.empty(st.batch_workspace_bytes(lays), dtype=torch.uint8, device=dev)
+    return dict(lays=lays, As=As, Ls=Ls, Ss=Ss, ws=ws, tile=tile)
+
+
+def run_batched(buf):
+    """pack + batched factor + batched selinv, enqueued on the current stream."""
+    for (A, lay), (ab, P, C) in zip(zip(buf["As"], buf["lays"]), buf["mats"]):
+        st.pack(ab, P, C, lay, out=A)
+    _, ld, info = st.factor_batched(buf["As"], buf["lays"], outs=buf["Ls"], workspace=buf["ws"])
+    _, info = st.selinv_batched(buf["Ls"], buf["lays"], outs=buf["Ss"], workspace=buf["ws"], info=info)
+    return ld, info
+
+
+def time_batched(mats, shapes, tile, reps: int = 1) -> Tuple[float, dict]:
+    """Milliseconds of one batched pass at this tile size (after one untimed pass)."""
+    import torch
+    buf = batch_buffers(mats, shapes, tile)
+    buf["mats"] = mats
+    run_batched(buf)
+    torch.cuda.synchronize()
+    e0, e1 = _events()
+    e0.record()
+    for _ in range(reps):
+        run_batched(buf)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps, buf
+
+
+def time_plain(mats, shapes, tile) -> List[float]:
+    """Milliseconds of pack + factor + selinv of each matrix alone (its own launches)."""
+    import torch
+    out = []
+    for (ab, P, C), (n, w, a) in zip(mats, shapes):
+        lay = st.layout(n, w, a, tile)
+        A = torch.empty(lay.total_doubles, dtype=torch.float64, device=ab.device)
+        L = torch.empty_like(A)
+        S = torch.empty_like(A)
+        wf = torch.empty(lay.factor_workspace_bytes, dtype=torch.uint8, device=ab.device)
+        wsl = torch.empty(lay.selinv_workspace_bytes, dtype=torch.uint8, device=ab.device)
+
+        def once():
+            st.pack(ab, P, C, lay, out=A)
+            st.factor(A, lay, out=L, workspace=wf)
+            st.selinv(L, lay, out=S, workspace=wsl)
+        once()
+        torch.cuda.synchronize()
+        e0, e1 = _events()
+        e0.record()
+        once()
+        e1.record()
+        torch.cuda.synchronize()
+        out.append(e0.elapsed_time(e1))
+        del A, L, S, wf, wsl
+    return out
+
+
+def tune_batch(mats, shapes, candidates: Sequence[int] = CANDIDATES) -> Tuple[int, Dict[int, float]]:
+    """(fastest tile size, {tile: ms of one batched pass})."""
+    import torch
+    ms = {}
+    for b in candidates:
+        t, buf = time_batched(mats, shapes, b)
+        ms[b] = t
+        del buf
+        torch.cuda.empty_cache()
+    return min(ms, key=ms.get), ms
