@@ -86,6 +86,7 @@ WORKLOADS = {
     "large": dict(nb=100000, w=1024, a=100, b=256, seed=1, cpu_nb=100000),
     "small": dict(nb=2000, w=32, a=20, b=64, seed=0, cpu_nb=2000),
     "batched": dict(),
+    "served": dict(),
 }
 WORK = WORKLOADS["large"]
 
@@ -99,6 +100,10 @@ def main() -> int:
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="batched: this tile size instead of the autotuner's")
+    ap.add_argument("--jobs", type=int, default=100, help="served: jobs per arrival rate")
+    ap.add_argument("--budget-gb", type=float, default=64.0, help="served: HBM budget of the serving loop")
+    ap.add_argument("--lanes", type=int, default=3, help="served: concurrent batches")
+    ap.add_argument("--max-batch", type=int, default=8, help="served: jobs per batch at most")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched: skip the plain-form timing and the per-matrix comparison (profiling runs)")
     args = ap.parse_args()
@@ -109,6 +114,8 @@ def main() -> int:
 
     if args.workload == "batched":
         return main_batched(args)
+    if args.workload == "served":
+        return main_served(args)
 
     import numpy as np
     import torch
@@ -325,6 +332,100 @@ def main_batched(args) -> int:
         "ok": ok,
         "bitwise_equal_to_single": same,
         "kernels": kinds,
+    }
+    print(json.dumps(out), flush=True)
+    return 0 if ok else 1
+
+
+def main_served(args) -> int:
+    """A Poisson stream of factor + selinv jobs (inputs.SERVE shapes) through
+    the serving loop (paper_2504_19171_amd/serve.py) and through the plain
+    FIFO (one job at a time), at 0.5 and 0.8 of the plain FIFO's capacity
+    measured on a prefix of the stream; p50/p99 latency and solves/s."""
+    import numpy as np
+    import torch
+    from paper_2504_19171_amd import autotune
+    from paper_2504_19171_amd import inputs
+    from paper_2504_19171_amd import serve
+
+    dev = torch.device("cuda:0")
+    t0 = time.perf_counter()
+    shapes = inputs.serve_shapes(args.jobs)
+    mats = [inputs.arrowhead_spd_device(nb, w, a, seed, dev) for (nb, w, a, seed) in shapes]
+    torch.cuda.synchronize()
+    print(f"bench: {len(shapes)} jobs drawn on the device in {time.perf_counter() - t0:.1f} s "
+          f"(n {min(s[0] + s[2] for s in shapes)}..{max(s[0] + s[2] for s in shapes)})", file=sys.stderr, flush=True)
+    if args.tile:
+        tile, tune_ms = args.tile, None
+    else:
+        k = min(16, len(shapes))
+        tile, tune_ms = autotune.tune_batch(mats[:k], [(nb + a, w, a) for (nb, w, a, _) in shapes[:k]])
+        print(f"bench: autotuner on the first {k} jobs {tune_ms} -> tile {tile}", file=sys.stderr, flush=True)
+
+    def jobs_at(arrivals):
+        return [serve.Job(k, nb, w, a, float(t), ab=m[0], P=m[1], C=m[2])
+                for k, ((nb, w, a, _), m, t) in enumerate(zip(shapes, mats, arrivals))]
+
+    # capacities: a prefix of the stream, all arrived at 0
+    npre = min(40, len(shapes))
+    done = serve.serve_plain(jobs_at([0.0] * npre)[:npre], tile)
+    mu = npre / max(j.done for j in done)
+    srv = serve.Server(budget=int(args.budget_gb * 2**30), tile=tile, lanes=args.lanes, max_batch=args.max_batch)
+    done = srv.run(jobs_at([0.0] * npre)[:npre])
+    mu_served = npre / max(j.done for j in done)
+    print(f"bench: capacity on the first {npre} jobs: plain FIFO {mu:.2f} jobs/s, served {mu_served:.2f} jobs/s",
+          file=sys.stderr, flush=True)
+    rates = {}
+    ok = True
+    for frac in (0.5, 0.8, 1.5):
+        rng = np.random.default_rng(33)
+        arr = np.cumsum(rng.exponential(1.0 / (frac * mu), len(shapes)))
+        arr -= arr[0]
+        res = {}
+        for form in ("served", "plain"):
+            jobs = jobs_at(arr)
+            if form == "served":
+                srv = serve.Server(budget=int(args.budget_gb * 2**30), tile=tile, lanes=args.lanes,
+                                   max_batch=args.max_batch)
+                out = srv.run(jobs)
+            else:
+                out = serve.serve_plain(jobs, tile)
+            lat = np.array([j.done - j.arrival for j in out]) * 1e3
+            span = max(j.done for j in out) - min(j.arrival for j in out)
+            ok &= all(j.info == (0, 0) and np.isfinite(j.logdet) for j in out)
+            res[form] = {"latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                         "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+                         "solves_per_s": round(len(out) / span, 3)}
+            for j in jobs:
+                j.L = j.Sigma = None
+            torch.cuda.synchronize()
+            print(f"bench: {form} at {frac} x capacity: {res[form]}", file=sys.stderr, flush=True)
+        rates[str(frac)] = dict(qps=round(frac * mu, 3), **res)
+    top = rates["0.8"]["served"]
+    out = {
+        "metric": METRIC,
+        "value": top["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": len(shapes),
+        "warmup": 0,
+        "ms_per_step": round(1e3 / top["solves_per_s"], 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"served: {len(shapes)} jobs of a Poisson stream, n log-uniform on [2,000, 200,000], "
+                               "half-bandwidth log-uniform on [16, 1,024], arrow uniform on [0, 500], seeded N(0,1) "
+                               "band and arrow drawn on the device, diagonal = row |sum| + 1",
+                   "jobs": len(shapes), "tile": tile, "autotune_ms": tune_ms, "lanes": args.lanes,
+                   "max_batch": args.max_batch, "budget_gb": args.budget_gb,
+                   "rates_are_fractions_of": "the plain FIFO's capacity"},
+        "capacity_jobs_per_s": {"plain_fifo": round(mu, 3), "served": round(mu_served, 3), "on_jobs": npre},
+        "latency_ms_p50": top["latency_ms_p50"],
+        "latency_ms_p99": top["latency_ms_p99"],
+        "rates": rates,
+        "ok": bool(ok),
     }
     print(json.dumps(out), flush=True)
     return 0 if ok else 1

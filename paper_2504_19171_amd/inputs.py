@@ -111,3 +111,60 @@ def batch_shapes(count: int = BATCH["count"], seed: int = BATCH["seed"], nb_rang
         a = int(rng.integers(a_range[0], a_range[1] + 1))
         out.append((nb, w, a, BATCH["base"] + k))
     return out
+
+
+# The served workload: a stream of jobs whose total order n is log-uniform on
+# [2,000, 200,000], half-bandwidth log-uniform on [16, 1,024] (rounded) and
+# arrow width uniform on [0, 500]; the shapes come from one seeded stream and
+# job k is drawn with seed base + k.
+SERVE = dict(n_range=(2000, 200000), w_range=(16, 1024), a_range=(0, 500), seed=3, base=3000)
+
+
+def serve_shapes(count: int, seed: int = SERVE["seed"]):
+    """[(nb, w, a, seed_k)] of the first `count` jobs of the seeded served stream."""
+    rng = np.random.default_rng(seed)
+    lo, hi = SERVE["n_range"]
+    wl, wh = SERVE["w_range"]
+    out = []
+    for k in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(lo), np.log(hi)))))
+        w = int(round(np.exp(rng.uniform(np.log(wl), np.log(wh)))))
+        a = int(rng.integers(SERVE["a_range"][0], SERVE["a_range"][1] + 1))
+        a = min(a, n - 1)
+        out.append((n - a, w, a, SERVE["base"] + k))
+    return out
+
+
+def arrowhead_spd_device(nb: int, w: int, a: int, seed: int, device, diag_shift: float = 1.0):
+    """The same construction as arrowhead_spd, drawn on the device with a seeded
+    torch generator (a different random stream from the numpy one), for
+    workloads too large to draw on the host.  Returns (ab, P, C) device
+    tensors in the canonical band form (P, C None when a == 0)."""
+    import torch
+    nb, w, a = int(nb), int(w), int(a)
+    we = min(w, max(nb - 1, 0))
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    ab = torch.zeros((we + 1, nb), dtype=f64, device=device)
+    rowsum = torch.zeros(nb, dtype=f64, device=device)
+    if we:
+        ab[1:] = torch.randn((we, nb), generator=g, dtype=f64, device=device)
+        col = torch.arange(nb, device=device)
+        d = torch.arange(1, we + 1, device=device)[:, None]
+        ab[1:].masked_fill_(col[None, :] >= nb - d, 0.0)    # A[j+d, j] exists for j < nb - d
+        av = ab[1:].abs()
+        rowsum += av.sum(0)                                # row j, entries (j, j+d)
+        for dd in range(1, we + 1):                         # row j+d, entries (j+d, j)
+            rowsum[dd:] += av[dd - 1, : nb - dd]
+    P = C = None
+    if a:
+        P = torch.randn((a, nb), generator=g, dtype=f64, device=device)
+        Z = torch.randn((a, a), generator=g, dtype=f64, device=device)
+        Lo = torch.tril(Z, -1)
+        C = Lo + Lo.T
+        rowsum += P.abs().sum(0)
+        C.diagonal().copy_(P.abs().sum(1) + C.abs().sum(1) + diag_shift)
+    if nb:
+        ab[0] = rowsum + diag_shift
+    return ab, P, C
