@@ -189,6 +189,25 @@ int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* w
                           size_t workspace_bytes, void* stream);
 
 /*
+ * Trace of a product on the tile pattern, for the gradient of log det:
+ *   *out = sum_ij Sigma_ij B_ij  over the real entries (padding left out),
+ * with Sigma and B symmetric and stored in the tile layout of one matrix,
+ * Sigma as stiles_selinv writes it and B as stiles_pack writes it (diagonal
+ * tiles and the corner full, band tiles below the diagonal and arrow tiles
+ * standing for their mirrored upper parts too).  When the pattern of B lies
+ * in the tile pattern of L this is tr(A^{-1} B); with B = dA/dtheta it is
+ * d log det A / dtheta (Jacobi's formula; the paper's selected inverse is what
+ * makes it cheap, Sec. I).  Fixed summation order: repeatable bit for bit.
+ *   Sigma, B  device, tile layout (read only)
+ *   out       device, one double
+ *   workspace device, at least stiles_trace_workspace_bytes()
+ */
+size_t stiles_trace_workspace_bytes(void);
+int stiles_trace_product(const double* Sigma, const double* B, int64_t n, int64_t bandwidth,
+                         int64_t arrow, int32_t tile, double* out, void* workspace,
+                         size_t workspace_bytes, void* stream);
+
+/*
  * Per-kernel timing with HIP events (tracing support, not needed for results).
  * While enabled, every kernel the library enqueues is bracketed by a pair of
  * HIP events recorded on the same stream.  stiles_timing_collect() waits for

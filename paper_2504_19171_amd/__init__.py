@@ -7,4 +7,4 @@ for gfx950 behind the C ABI declared in ``include/stiles.h``; the Python module
 :mod:`paper_2504_19171_amd.stiles` marshals arguments to it.
 """
 
-__all__ = ["autotune", "inputs", "layout", "serve", "stiles"]
+__all__ = ["autotune", "grad", "inputs", "layout", "serve", "stiles"]

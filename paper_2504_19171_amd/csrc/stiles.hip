@@ -1192,6 +1192,57 @@ __global__ void kb_selinv_final(const BInst* bi) {
 }
 
 // ---------------------------------------------------------------------------
+// Trace of a product over the tile pattern (gradient of log det)
+// ---------------------------------------------------------------------------
+// sum_ij S_ij B_ij over the real entries of two symmetric matrices stored on
+// the same tile pattern: a diagonal band tile and the corner hold both
+// triangles (weight 1 each), a band tile below the diagonal and an arrow tile
+// the strictly lower part (weight 2: the upper part mirrors it); padding
+// (rows or columns past nb in the band, past a in the arrow) is left out.
+// Block g of TP_BLOCKS sums a contiguous range of the buffer in a fixed order
+// into part[g]; k_trace_final adds the parts in order (Neumaier), so the
+// result does not depend on timing.
+#define TP_BLOCKS 1024
+__global__ __launch_bounds__(NT) void k_trace_part(const double* __restrict__ S, const double* __restrict__ B, Lay L,
+                                                   double* part) {
+    __shared__ double red[NT];
+    const int64_t per = (L.total + TP_BLOCKS - 1) / TP_BLOCKS;
+    const int64_t lo = blockIdx.x * per, hi = std::min<int64_t>(L.total, lo + per);
+    const int64_t b = L.b, b2 = b * b;
+    double acc = 0.0;
+    for (int64_t idx = lo + threadIdx.x; idx < hi; idx += NT) {
+        double wgt = 0.0;
+        if (idx < L.off_arrow) {
+            const int64_t t = idx / b2, e = idx % b2;
+            const int64_t J = t / (L.bt + 1), d = t % (L.bt + 1);
+            const int64_t i = (J + d) * b + e % b, j = J * b + e / b;
+            if (J + d < L.nt && i < L.nb && j < L.nb) wgt = d == 0 ? 1.0 : 2.0;
+        } else if (idx < L.off_corner) {
+            const int64_t e = idx - L.off_arrow;
+            const int64_t J = e / ((int64_t)L.ap * b), f = e % ((int64_t)L.ap * b);
+            if (f % L.ap < L.a && J * b + f / L.ap < L.nb) wgt = 2.0;
+        } else {
+            const int64_t e = idx - L.off_corner;
+            if (e % L.ap < L.a && e / L.ap < L.a) wgt = 1.0;
+        }
+        if (wgt != 0.0) acc = fma(wgt * S[idx], B[idx], acc);
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int o = NT / 2; o > 0; o >>= 1) {
+        if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+__global__ void k_trace_final(const double* part, double* out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double s = 0.0, c = 0.0;
+    for (int g = 0; g < TP_BLOCKS; ++g) neumaier(s, c, part[g]);
+    *out = s + c;
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
@@ -1603,6 +1654,25 @@ int stiles_selinv(const double* Lm, double* S, int64_t n, int64_t bandwidth, int
     }
     LAUNCH(STILES_TK_OTHER, k_selinv_final, dim3(1), dim3(64), 0, st, (const int*)v.winfo, (const int*)v.err,
            (int*)info);
+    return 0;
+}
+
+size_t stiles_trace_workspace_bytes(void) { return sizeof(double) * TP_BLOCKS; }
+
+int stiles_trace_product(const double* Sigma, const double* B, int64_t n, int64_t bandwidth, int64_t arrow,
+                         int32_t tile, double* out, void* workspace, size_t workspace_bytes, void* stream) {
+    stiles_layout lay;
+    int rc = make_layout(n, bandwidth, arrow, tile, &lay);
+    if (rc) return rc - 2;
+    if (!Sigma) return -1;
+    if (!B) return -2;
+    if (!out) return -7;
+    if (!workspace || workspace_bytes < stiles_trace_workspace_bytes()) return -8;
+    hipStream_t st = S_(stream);
+    const Lay L = to_dev(lay);
+    double* part = (double*)workspace;
+    LAUNCH(STILES_TK_OTHER, k_trace_part, dim3(TP_BLOCKS), dim3(NT), 0, st, Sigma, B, L, part);
+    LAUNCH(STILES_TK_OTHER, k_trace_final, dim3(1), dim3(64), 0, st, (const double*)part, out);
     return 0;
 }
 

@@ -38,6 +38,8 @@ EXPORTED = (
     "stiles_batch_workspace_bytes",
     "stiles_factor_batched",
     "stiles_selinv_batched",
+    "stiles_trace_workspace_bytes",
+    "stiles_trace_product",
 )
 
 TIMING_KINDS = ("potrf", "trsm", "update", "phase1", "phase2", "factor", "other")
@@ -100,6 +102,10 @@ def load(path: Optional[str] = None):
     lib.stiles_timing_collect.restype = ctypes.c_int
     lib.stiles_version.argtypes = []
     lib.stiles_version.restype = ctypes.c_int
+    lib.stiles_trace_workspace_bytes.argtypes = []
+    lib.stiles_trace_workspace_bytes.restype = _sz
+    lib.stiles_trace_product.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _sz, _vp]
+    lib.stiles_trace_product.restype = ctypes.c_int
     lib.stiles_batch_workspace_bytes.argtypes = [ctypes.POINTER(_CBatchItem), _i32]
     lib.stiles_batch_workspace_bytes.restype = _sz
     lib.stiles_factor_batched.argtypes = [ctypes.POINTER(_CBatchItem), _i32, _vp, _sz, _vp]
@@ -313,3 +319,22 @@ def selinv_batched(Ls, lays, outs=None, workspace=None, info=None, stream=None):
     if rc != 0:
         raise StilesError(rc, "stiles_selinv_batched")
     return Ss, info
+
+
+def trace_product(Sigma, B, lay: Layout, out=None, workspace=None, stream=None):
+    """sum_ij Sigma_ij B_ij over the real entries of the tile pattern (a
+    1-element device tensor): tr(A^{-1} B) for Sigma from :func:`selinv` and B
+    packed by :func:`pack` with its pattern inside L's."""
+    import torch
+    Sigma = _dev_f64(Sigma, "Sigma")
+    B = _dev_f64(B, "B")
+    dev = Sigma.device
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=dev)
+    ws = workspace if workspace is not None else torch.empty(int(load().stiles_trace_workspace_bytes()),
+                                                             dtype=torch.uint8, device=dev)
+    rc = load().stiles_trace_product(Sigma.data_ptr(), B.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                                     out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    if rc != 0:
+        raise StilesError(rc, "stiles_trace_product")
+    return out
