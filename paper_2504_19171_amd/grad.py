@@ -44,6 +44,7 @@ class SpatioTemporal:
         g.manual_seed(int(seed))
         self.X = (torch.randn((self.nb, self.a), generator=g, dtype=torch.float64, device=device)
                   if self.a else None)
+        self._XtX = None     # X^T X, formed on first use (it does not depend on theta)
 
     @staticmethod
     def path_laplacian_diag(m: int):
@@ -99,8 +100,10 @@ class SpatioTemporal:
         ab[0] += math.exp(t2) + (1.0 if self.with_ztz else 0.0)
         if not self.a:
             return ab, None, None
+        if self._XtX is None or self._XtX[0] is not self.X:
+            self._XtX = (self.X, self.X.T @ self.X)
         P = self.X.T.contiguous()
-        C = self.X.T @ self.X + math.exp(t2) * torch.eye(self.a, dtype=torch.float64, device=self.dev)
+        C = self._XtX[1] + math.exp(t2) * torch.eye(self.a, dtype=torch.float64, device=self.dev)
         return ab, P, C
 
     def derivatives(self, theta):

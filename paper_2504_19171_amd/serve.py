@@ -53,6 +53,19 @@ def job_bytes(lay: st.Layout) -> int:
     return 2 * 8 * lay.total_doubles + max(lay.factor_workspace_bytes, lay.selinv_workspace_bytes) + 4096
 
 
+def admit(queue: List[Job], room: int, max_batch: int) -> List[Job]:
+    """Take the next batch off the head of the queue, in arrival order: jobs
+    join while they fit the free bytes `room` and the batch has fewer than
+    `max_batch` jobs; the first job that does not fit stops the batch (no job
+    overtakes an earlier one)."""
+    batch = []
+    while queue and len(batch) < max_batch and queue[0].nbytes <= room:
+        j = queue.pop(0)
+        batch.append(j)
+        room -= j.nbytes
+    return batch
+
+
 @dataclass
 class _Lane:
     stream: object
@@ -148,11 +161,7 @@ class Server:
             for lane in self.lanes:
                 if lane.jobs or not queue:
                     continue
-                batch, room = [], self.budget - self.in_use
-                while queue and len(batch) < self.max_batch and queue[0].nbytes <= room:
-                    j = queue.pop(0)
-                    batch.append(j)
-                    room -= j.nbytes
+                batch = admit(queue, self.budget - self.in_use, self.max_batch)
                 if batch:
                     self.in_use += sum(j.nbytes for j in batch)
                     self._launch(lane, batch, clock_ev, t0)
