@@ -189,6 +189,22 @@ int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* w
                           size_t workspace_bytes, void* stream);
 
 /*
+ * Full inverse: every entry of A^{-1}, by the backward recurrence of Phase 2
+ * (Sec. III-D) taken over all tile rows instead of the rows of S(J) -- the
+ * full-inversion case of the selection spectrum (Sec. III-B) -- after Phase 1.
+ * Dense output, so for modest n: the workspace holds a dense padded copy,
+ * (N b + a_p)^2 doubles, and the work grows as n^2 (w + a).
+ *   L         device, tile layout, a factor produced by stiles_factor (read only)
+ *   Ainv      device, n x n column-major (leading dimension n), full symmetric
+ *   info      device, one int32: 0, or STILES_EBADL as for stiles_selinv
+ *   workspace device, at least stiles_inverse_workspace_bytes()
+ */
+size_t stiles_inverse_workspace_bytes(const stiles_layout* lay);
+int stiles_inverse(const double* L, double* Ainv, int64_t n, int64_t bandwidth, int64_t arrow,
+                   int32_t tile, int32_t* info, void* workspace, size_t workspace_bytes,
+                   void* stream);
+
+/*
  * Trace of a product on the tile pattern, for the gradient of log det:
  *   *out = sum_ij Sigma_ij B_ij  over the real entries (padding left out),
  * with Sigma and B symmetric and stored in the tile layout of one matrix,

@@ -431,17 +431,27 @@ __device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, cons
             for (int r = 0; r < 4; ++r)
                 ov[x][y][r] = ld_s(O, (uint32_t)((16 * ra[x] + li) + (16 * rb[y] + 4 * r + lk) * u.ldo));
         }
-    for (int p = 0; p < np; ++p) {
-        if (!col_wait(sc, ftr + u.ga, ta, p + 1, sh)) return false;
-        if (!col_wait(sc, ftr + u.gb, tb, p + 1, sh)) return false;
-        double av[2][4], bv[2][4];
+    // the operands of panel p + 1 are loaded (once its TRSM steps are
+    // announced) while panel p is multiplied
+    double av[2][4], bv[2][4], an[2][4], bn[2][4];
+    auto load = [&](double (&a)[2][4], double (&b)[2][4], int p) {
 #pragma unroll
         for (int x = 0; x < 2; ++x)
 #pragma unroll
             for (int kk = 0; kk < 4; ++kk) {
-                av[x][kk] = ld_coh_s(A, (uint32_t)((16 * ra[x] + li) + (16 * p + 4 * kk + lk) * u.lda));
-                bv[x][kk] = ld_coh_s(B, (uint32_t)((16 * rb[x] + li) + (16 * p + 4 * kk + lk) * u.ldb));
+                a[x][kk] = ld_coh_s(A, (uint32_t)((16 * ra[x] + li) + (16 * p + 4 * kk + lk) * u.lda));
+                b[x][kk] = ld_coh_s(B, (uint32_t)((16 * rb[x] + li) + (16 * p + 4 * kk + lk) * u.ldb));
             }
+    };
+    if (!col_wait(sc, ftr + u.ga, ta, 1, sh)) return false;
+    if (!col_wait(sc, ftr + u.gb, tb, 1, sh)) return false;
+    load(av, bv, 0);
+    for (int p = 0; p < np; ++p) {
+        if (p + 1 < np) {
+            if (!col_wait(sc, ftr + u.ga, ta, p + 2, sh)) return false;
+            if (!col_wait(sc, ftr + u.gb, tb, p + 2, sh)) return false;
+            load(an, bn, p + 1);
+        }
         // element r of acc[x][y]: sum_k A[16 ra + li][k] B[16 rb + 4r + lk][k]
 #pragma unroll
         for (int kk = 0; kk < 4; ++kk)
@@ -450,6 +460,13 @@ __device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, cons
 #pragma unroll
                 for (int y = 0; y < 2; ++y)
                     acc[x][y] = __builtin_amdgcn_mfma_f64_16x16x4f64(bv[y][kk], av[x][kk], acc[x][y], 0, 0, 0);
+#pragma unroll
+        for (int x = 0; x < 2; ++x)
+#pragma unroll
+            for (int kk = 0; kk < 4; ++kk) {
+                av[x][kk] = an[x][kk];
+                bv[x][kk] = bn[x][kk];
+            }
     }
 #pragma unroll
     for (int x = 0; x < 2; ++x)
@@ -1243,6 +1260,113 @@ __global__ void k_trace_final(const double* part, double* out) {
 }
 
 // ---------------------------------------------------------------------------
+// Full inversion (every entry of A^{-1})
+// ---------------------------------------------------------------------------
+// The recurrence of Phase 2 taken over every tile row instead of the rows of
+// S(J): in the padded index space (band rows 0 .. N b - 1, then the a_p arrow
+// rows), with D the dense symmetric inverse (leading dimension np),
+//   D[R, J] = -sum_{k in S(J)} D[R, k] Lhat_{k,J}   for all rows R below block J,
+//   D[J, J] = X_J^T X_J - sum_{k in S(J)} Lhat_{k,J}^T D[k, J],
+// for J = N-1 .. 0 after the corner D[A, A] = X_A^T X_A (Sec. III-D; the
+// full-inversion case of Sec. III-B).  Only Lhat_{k,J} with k in S(J) is
+// non-zero, so each block column is one product over the s band tiles and the
+// arrow.  Every value goes to both triangles, so a later column reads D[i, k]
+// for any i directly.
+
+// Diagonal blocks X_J^T X_J (and the corner's) into D.
+__global__ __launch_bounds__(NT) void k_inv_lauum(const double* W, double* D, int64_t ldd, Lay L) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    const int per = lauum_per(L);
+    const int64_t J = blockIdx.x / per;
+    const int t = blockIdx.x % per;
+    const int nb64 = L.b / 64, nab = arrow_blocks(L.ap);
+    const double* X;
+    double* O;
+    int m;
+    int64_t ld;
+    if (J < L.nt) {
+        if (t >= nb64 * (nb64 + 1) / 2) return;
+        X = W + L.band(J, 0); m = L.b; ld = L.b;
+        O = D + J * L.b + J * L.b * ldd;
+    } else {
+        if (t >= nab * (nab + 1) / 2) return;
+        X = W + L.corner(); m = L.ap; ld = L.ap;
+        const int64_t o = L.nt * (int64_t)L.b;
+        O = D + o + o * ldd;
+    }
+    int rb, cb;
+    tri_decode(t, rb, cb);
+    const int k0 = rb * 64;
+    const int va = imin_(64, m - rb * 64), vb = imin_(64, m - cb * 64);
+    GAcc g;
+    gacc_zero(g);
+    gemm_acc(g, opnd(X + k0 + (int64_t)rb * 64 * ld, ld, 1, va), opnd(X + k0 + (int64_t)cb * 64 * ld, ld, 0, vb),
+             m - k0, smem);
+    gemm_store_sym(g, smem, 1.0, 0.0, nullptr, 0, O + rb * 64 + (int64_t)cb * 64 * ldd,
+                   O + cb * 64 + (int64_t)rb * 64 * ldd, ldd, rb == cb, va, vb);
+}
+
+// D[R, J] for the rows R = (J+1) b .. np-1; block (row block, column block)
+// of 64 x 64, mirrored into D[J, R].
+__global__ __launch_bounds__(NT) void k_inv_column(const double* W, double* D, int64_t ldd, Lay L, int64_t J) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    const int nb64 = L.b / 64;
+    const int64_t r0 = (J + 1) * L.b;
+    const int rbk = blockIdx.x / nb64, cb = blockIdx.x % nb64;
+    const int64_t i0 = r0 + (int64_t)rbk * 64;
+    const int mv = (int)std::min<int64_t>(64, ldd - i0);
+    const int s = L.s(J);
+    const int64_t ca = L.nt * (int64_t)L.b;   // first arrow column
+    const int64_t c0 = J * L.b + cb * 64;
+    GAcc g;
+    gacc_zero(g);
+    for (int d = 1; d <= s; ++d)
+        gemm_acc(g, opnd(D + i0 + (J + d) * L.b * ldd, ldd, 0, mv), opnd(W + L.band(J, d) + (int64_t)cb * 64 * L.b, L.b, 0),
+                 L.b, smem);
+    if (L.ap > 0)
+        gemm_acc(g, opnd(D + i0 + ca * ldd, ldd, 0, mv), opnd(W + L.arrow(J) + (int64_t)cb * 64 * L.ap, L.ap, 0),
+                 L.ap, smem);
+    gemm_store_sym(g, smem, -1.0, 0.0, nullptr, 0, D + i0 + c0 * ldd, D + c0 + i0 * ldd, ldd, 0, mv, 64);
+}
+
+// D[J, J] -= Lhat_{S,J}^T D[S, J], lower 64 x 64 blocks, mirrored.
+__global__ __launch_bounds__(NT) void k_inv_diag(const double* W, double* D, int64_t ldd, Lay L, int64_t J) {
+    __shared__ double smem[GB_SMEM_DOUBLES];
+    int rb, cb;
+    tri_decode(blockIdx.x, rb, cb);
+    const int s = L.s(J);
+    const int64_t ca = L.nt * (int64_t)L.b;
+    const int64_t j0 = J * L.b;
+    GAcc g;
+    gacc_zero(g);
+    for (int d = 1; d <= s; ++d) {
+        const double* Lh = W + L.band(J, d);
+        gemm_acc(g, opnd(Lh + (int64_t)rb * 64 * L.b, L.b, 1), opnd(D + (J + d) * L.b + (j0 + cb * 64) * ldd, ldd, 0),
+                 L.b, smem);
+    }
+    if (L.ap > 0) {
+        const double* Lh = W + L.arrow(J);
+        gemm_acc(g, opnd(Lh + (int64_t)rb * 64 * L.ap, L.ap, 1), opnd(D + ca + (j0 + cb * 64) * ldd, ldd, 0), L.ap,
+                 smem);
+    }
+    double* O = D + j0 + j0 * ldd;
+    gemm_store_sym(g, smem, -1.0, 1.0, O + rb * 64 + (int64_t)cb * 64 * ldd, ldd, O + rb * 64 + (int64_t)cb * 64 * ldd,
+                   O + cb * 64 + (int64_t)rb * 64 * ldd, ldd, rb == cb, 64, 64);
+}
+
+// The real rows and columns of D into the n x n output (band index i -> i,
+// arrow index nb + r -> N b + r).
+__global__ __launch_bounds__(NT) void k_inv_compact(const double* D, int64_t ldd, Lay L, double* O) {
+    const int64_t n = L.nb + L.a;
+    const int64_t shift = L.nt * (int64_t)L.b - L.nb;
+    for (int64_t idx = blockIdx.x * (int64_t)NT + threadIdx.x; idx < n * n; idx += (int64_t)gridDim.x * NT) {
+        const int64_t i = idx % n, j = idx / n;
+        const int64_t si = i < L.nb ? i : i + shift, sj = j < L.nb ? j : j + shift;
+        O[idx] = D[si + sj * ldd];
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
 
@@ -1658,6 +1782,57 @@ int stiles_selinv(const double* Lm, double* S, int64_t n, int64_t bandwidth, int
 }
 
 size_t stiles_trace_workspace_bytes(void) { return sizeof(double) * TP_BLOCKS; }
+
+// padded order of the dense inverse: N b band rows and a_p arrow rows
+static int64_t inv_order(const stiles_layout& l) { return l.nt * (int64_t)l.tile + l.arrow_ld; }
+
+size_t stiles_inverse_workspace_bytes(const stiles_layout* lay) {
+    if (!lay) return 0;
+    const int64_t np = inv_order(*lay);
+    return sws_bytes(*lay) + sizeof(double) * (size_t)(np * np);
+}
+
+int stiles_inverse(const double* Lm, double* Ainv, int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile,
+                   int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
+    stiles_layout lay;
+    int rc = make_layout(n, bandwidth, arrow, tile, &lay);
+    if (rc) return rc - 2;
+    if (!Lm) return -1;
+    if (!Ainv) return -2;
+    if (!info) return -7;
+    if (!workspace || workspace_bytes < stiles_inverse_workspace_bytes(&lay)) return -8;
+    hipStream_t st = S_(stream);
+    const Lay L = to_dev(lay);
+    const SelinvWs v = selinv_ws(L, (char*)workspace);
+    double* D = (double*)((char*)workspace + sws_bytes(lay));
+    const int64_t np = inv_order(lay);
+    const int nb64 = L.b / 64, nab = arrow_blocks(L.ap);
+
+    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, v.winfo, 0);
+    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, v.err, 0);
+    LAUNCH(STILES_TK_OTHER, k_zero_ints, dim3(grid_for(np * np * 2)), dim3(NT), 0, st, (int*)D, np * np * 2);
+    // Phase 1: X_J, Lhat (as for stiles_selinv)
+    LAUNCH(STILES_TK_PHASE1, k_trtri_all, dim3((unsigned)(L.nt + (L.ap > 0))), dim3(NT), 0, st, Lm, v.W, L, v.winfo);
+    {
+        const int64_t g = L.nt * (int64_t)(L.bt * nb64 + nab) * nb64;
+        if (g > 0) LAUNCH(STILES_TK_PHASE1, k_trmm_all, dim3((unsigned)g), dim3(NT), 0, st, Lm, v.W, L);
+    }
+    LAUNCH(STILES_TK_PHASE1, k_inv_lauum, dim3((unsigned)((L.nt + (L.ap > 0)) * (int64_t)lauum_per(L))), dim3(NT), 0,
+           st, (const double*)v.W, D, np, L);
+    for (int64_t J = L.nt - 1; J >= 0; --J) {
+        const int64_t rows = np - (J + 1) * L.b;
+        if (rows > 0) {
+            const int64_t g = (rows + 63) / 64 * nb64;
+            LAUNCH(STILES_TK_PHASE2, k_inv_column, dim3((unsigned)g), dim3(NT), 0, st, (const double*)v.W, D, np, L, J);
+            LAUNCH(STILES_TK_PHASE2, k_inv_diag, dim3((unsigned)(nb64 * (nb64 + 1) / 2)), dim3(NT), 0, st,
+                   (const double*)v.W, D, np, L, J);
+        }
+    }
+    LAUNCH(STILES_TK_OTHER, k_inv_compact, dim3(grid_for(lay.n * lay.n)), dim3(NT), 0, st, (const double*)D, np, L,
+           Ainv);
+    LAUNCH(STILES_TK_OTHER, k_selinv_final, dim3(1), dim3(64), 0, st, (const int*)v.winfo, (const int*)v.err, (int*)info);
+    return 0;
+}
 
 int stiles_trace_product(const double* Sigma, const double* B, int64_t n, int64_t bandwidth, int64_t arrow,
                          int32_t tile, double* out, void* workspace, size_t workspace_bytes, void* stream) {

@@ -40,6 +40,8 @@ EXPORTED = (
     "stiles_selinv_batched",
     "stiles_trace_workspace_bytes",
     "stiles_trace_product",
+    "stiles_inverse_workspace_bytes",
+    "stiles_inverse",
 )
 
 TIMING_KINDS = ("potrf", "trsm", "update", "phase1", "phase2", "factor", "other")
@@ -102,6 +104,10 @@ def load(path: Optional[str] = None):
     lib.stiles_timing_collect.restype = ctypes.c_int
     lib.stiles_version.argtypes = []
     lib.stiles_version.restype = ctypes.c_int
+    lib.stiles_inverse_workspace_bytes.argtypes = [ctypes.POINTER(_CLayout)]
+    lib.stiles_inverse_workspace_bytes.restype = _sz
+    lib.stiles_inverse.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _sz, _vp]
+    lib.stiles_inverse.restype = ctypes.c_int
     lib.stiles_trace_workspace_bytes.argtypes = []
     lib.stiles_trace_workspace_bytes.restype = _sz
     lib.stiles_trace_product.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _sz, _vp]
@@ -338,3 +344,23 @@ def trace_product(Sigma, B, lay: Layout, out=None, workspace=None, stream=None):
     if rc != 0:
         raise StilesError(rc, "stiles_trace_product")
     return out
+
+
+def inverse(L, lay: Layout, out=None, workspace=None, stream=None):
+    """Every entry of A^{-1} (n x n, column-major, full symmetric) from the factor L;
+    returns (Ainv, info) on the device."""
+    import torch
+    L = _dev_f64(L, "L")
+    dev = L.device
+    n = lay.n
+    Ainv = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=dev)
+    ws = workspace
+    if ws is None:
+        ws = torch.empty(int(load().stiles_inverse_workspace_bytes(ctypes.byref(lay._c()))), dtype=torch.uint8,
+                         device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    rc = load().stiles_inverse(L.data_ptr(), Ainv.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                               info.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+    if rc != 0:
+        raise StilesError(rc, "stiles_inverse")
+    return Ainv, info

@@ -73,6 +73,19 @@ def test_entry_points_reject_bad_arguments_before_any_gpu_call():
     assert lib.stiles_pack(None, 8, 8, 8, 100, 4, 3, 64, None) == -1
     assert lib.stiles_pack(8, None, 8, 8, 100, 4, 3, 64, None) == -2
     assert lib.stiles_pack(8, 8, 8, 8, 100, 4, 3, 40, None) == -8
+    wsi = lib.stiles_inverse_workspace_bytes(ctypes.byref(lay._c()))
+    np_ = lay.nt * lay.tile + lay.arrow_ld
+    assert wsi >= lay.selinv_workspace_bytes + 8 * np_ * np_
+    assert lib.stiles_inverse(None, 16, 100, 4, 3, 64, 8, 8, wsi, None) == -1
+    assert lib.stiles_inverse(8, None, 100, 4, 3, 64, 8, 8, wsi, None) == -2
+    assert lib.stiles_inverse(8, 16, 100, 4, 3, 64, None, 8, wsi, None) == -7
+    assert lib.stiles_inverse(8, 16, 100, 4, 3, 64, 8, 8, wsi - 1, None) == -8
+    wst = lib.stiles_trace_workspace_bytes()
+    assert lib.stiles_trace_product(None, 8, 100, 4, 3, 64, 8, 8, wst, None) == -1
+    assert lib.stiles_trace_product(8, None, 100, 4, 3, 64, 8, 8, wst, None) == -2
+    assert lib.stiles_trace_product(8, 8, 100, 4, 3, 64, None, 8, wst, None) == -7
+    assert lib.stiles_trace_product(8, 8, 100, 4, 3, 64, 8, 8, wst - 1, None) == -8
+    assert lib.stiles_trace_product(8, 8, 100, 4, 3, 40, 8, 8, wst, None) == -6
     for code in (0, 5, -1, -100, -101, -102, -103):
         assert st.strerror(code)
 
