@@ -189,6 +189,29 @@ int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* w
                           size_t workspace_bytes, void* stream);
 
 /*
+ * Selection (Sec. III-B, selection step and symbolic inversion).  A selected
+ * (i, j) lies in tile column J (J = j / b in the band part, or the corner);
+ * the recurrence for tile column J reads only tile columns to its right, so
+ * the closure of a selection inside the tile pattern of L is every tile column
+ * from the leftmost selected one to the last, and nothing to the left of it is
+ * computed.
+ *
+ * stiles_selinv_range: stiles_selinv restricted to the tile columns
+ *   J >= first_column (0 <= first_column <= N; N: the corner alone).  Those
+ *   columns and the corner of Sigma come out as from stiles_selinv, bit for
+ *   bit; the other band and arrow tiles of Sigma are left undefined.
+ *   Arguments as stiles_selinv, with first_column as argument 7.
+ * stiles_gather: out[k] = Sigma(ij[2k], ij[2k+1]) (either order) for count
+ *   pairs (device arrays: ij int64 [2 count], out double [count]); NaN for a
+ *   pair outside the tile pattern of L or outside the matrix.
+ */
+int stiles_selinv_range(const double* L, double* Sigma, int64_t n, int64_t bandwidth, int64_t arrow,
+                        int32_t tile, int64_t first_column, int32_t* info, void* workspace,
+                        size_t workspace_bytes, void* stream);
+int stiles_gather(const double* Sigma, int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile,
+                  const int64_t* ij, int64_t count, double* out, void* stream);
+
+/*
  * Full inverse: every entry of A^{-1}, by the backward recurrence of Phase 2
  * (Sec. III-D) taken over all tile rows instead of the rows of S(J) -- the
  * full-inversion case of the selection spectrum (Sec. III-B) -- after Phase 1.

@@ -592,9 +592,10 @@ __device__ inline void trtri_body(const double* Lm, double* W, const Lay& L, int
     }
     if (threadIdx.x == 0 && bad) atomicExch(info, STILES_EBADL);
 }
-__global__ __launch_bounds__(NT) void k_trtri_all(const double* Lm, double* W, Lay L, int* info) {
+// (j0: first tile column; the launches of a selection start there)
+__global__ __launch_bounds__(NT) void k_trtri_all(const double* Lm, double* W, Lay L, int* info, int64_t j0) {
     __shared__ double smem[TRTRI_SMEM_DOUBLES];
-    trtri_body(Lm, W, L, info, blockIdx.x, smem);
+    trtri_body(Lm, W, L, info, (int)(blockIdx.x + j0), smem);
 }
 
 // Rows of the panel below tile J (band tiles J+1..J+s, then the arrow tile),
@@ -640,9 +641,10 @@ __device__ inline void trmm_body(const double* Lm, double* W, const Lay& L, int 
              L.b - k0, smem);
     gemm_store(g, smem, 1.0, 0.0, nullptr, 0, Cw + (int64_t)k0 * ld, ld, valid, 64);
 }
-__global__ __launch_bounds__(NT) void k_trmm_all(const double* Lm, double* W, Lay L) {
+__global__ __launch_bounds__(NT) void k_trmm_all(const double* Lm, double* W, Lay L, int64_t j0) {
     __shared__ double smem[GB_SMEM_DOUBLES];
-    trmm_body(Lm, W, L, blockIdx.x, smem);
+    const int nb64 = L.b / 64;
+    trmm_body(Lm, W, L, (int)(blockIdx.x + j0 * (L.bt * nb64 + arrow_blocks(L.ap)) * nb64), smem);
 }
 
 // Phase 2 initial value of each diagonal tile, "LAUUM": Sigma_JJ = X_J^T X_J
@@ -680,9 +682,9 @@ __device__ inline void lauum_body(const double* W, double* S, const Lay& L, int 
     gemm_store_sym(g, smem, 1.0, 0.0, nullptr, 0, O + rb * 64 + (int64_t)cb * 64 * ld,
                    O + cb * 64 + (int64_t)rb * 64 * ld, ld, rb == cb, va, vb);
 }
-__global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, Lay L) {
+__global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, Lay L, int64_t j0) {
     __shared__ double smem[GB_SMEM_DOUBLES];
-    lauum_body(W, S, L, blockIdx.x, smem);
+    lauum_body(W, S, L, (int)(blockIdx.x + j0 * lauum_per(L)), smem);
 }
 
 #define ARW (-1)   // "the arrow" in place of a band tile offset
@@ -1260,6 +1262,34 @@ __global__ void k_trace_final(const double* part, double* out) {
 }
 
 // ---------------------------------------------------------------------------
+// Selected entries read off the tile layout
+// ---------------------------------------------------------------------------
+// out[k] = Sigma(ij[2k], ij[2k+1]) (either order: Sigma is symmetric); NaN
+// for a pair outside the tile pattern of L or outside the matrix.
+__global__ __launch_bounds__(NT) void k_gather(const double* S, Lay L, const int64_t* ij, int64_t count, double* out) {
+    const int64_t n = L.nb + L.a;
+    for (int64_t k = blockIdx.x * (int64_t)NT + threadIdx.x; k < count; k += (int64_t)gridDim.x * NT) {
+        int64_t i = ij[2 * k], j = ij[2 * k + 1];
+        if (i < j) { const int64_t t = i; i = j; j = t; }
+        double v = __builtin_nan("");
+        if (j >= 0 && i < n) {
+            if (j < L.nb) {
+                const int64_t J = j / L.b, c = j - J * L.b;
+                if (i < L.nb) {
+                    const int64_t I = i / L.b;
+                    if (I - J <= L.bt) v = S[L.band(J, (int)(I - J)) + (i - I * L.b) + c * L.b];
+                } else {
+                    v = S[L.arrow(J) + (i - L.nb) + c * L.ap];
+                }
+            } else {
+                v = S[L.corner() + (i - L.nb) + (j - L.nb) * L.ap];
+            }
+        }
+        out[k] = v;
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Full inversion (every entry of A^{-1})
 // ---------------------------------------------------------------------------
 // The recurrence of Phase 2 taken over every tile row instead of the rows of
@@ -1729,6 +1759,57 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     return 0;
 }
 
+// Selected inverse on the tile columns J >= jf (and the corner): Phase 1 of
+// the columns from jf - 1 on (the first Phase 2 group also starts the early
+// part of column jf - 1), Phase 2 groups N-1 .. jf.  jf = 0 is the whole
+// pattern.
+static int selinv_impl(const double* Lm, double* S, const stiles_layout& lay, int64_t jf, int32_t* info,
+                       void* workspace, hipStream_t st) {
+    Lay L = to_dev(lay);
+    const SelinvWs v = selinv_ws(L, (char*)workspace);
+    const int nb64 = L.b / 64, nab = arrow_blocks(L.ap);
+    int64_t ntasks = 0;
+    for (int64_t J = jf; J < L.nt; ++J) ntasks += p2_group_tasks(L, J);
+    if (ntasks > 0x7fffffff) return -3;
+    const int64_t j1 = std::max<int64_t>(0, jf - 1);
+
+    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, v.winfo, 0);
+    if (L.bt > 0) {
+        const int64_t tail = (int64_t)L.bt * (L.bt + 1) / 2 * L.b * L.b;
+        LAUNCH(STILES_TK_OTHER, k_zero_unused, dim3(grid_for(tail)), dim3(NT), 0, st, S, L);
+    }
+    // Phase 1
+    LAUNCH(STILES_TK_PHASE1, k_trtri_all, dim3((unsigned)(L.nt - j1 + (L.ap > 0))), dim3(NT), 0, st, Lm, v.W, L, v.winfo,
+           j1);
+    {
+        const int64_t g = (L.nt - j1) * (int64_t)(L.bt * nb64 + nab) * nb64;
+        if (g > 0) {
+            LAUNCH(STILES_TK_PHASE1, k_trmm_all, dim3((unsigned)g), dim3(NT), 0, st, Lm, v.W, L, j1);
+        }
+    }
+    {
+        const int64_t g = (L.nt - j1 + (L.ap > 0)) * (int64_t)lauum_per(L);
+        LAUNCH(STILES_TK_PHASE1, k_lauum_all, dim3((unsigned)g), dim3(NT), 0, st, (const double*)v.W, S, L, j1);
+    }
+    // Phase 2, bottom-right to top-left, one persistent launch
+    DevInfo di;
+    if (dev_info(&di)) return STILES_EHIP;
+    const P2 p = make_p2(S, v, L, (int)ntasks);
+    Sched sc;
+    sc.ticket = v.ticket;
+    sc.err = v.err;
+    sc.spin_limit = spin_limit_ticks(di);
+    sc.withhold = debug_withhold();
+    LAUNCH(STILES_TK_OTHER, k_p2_setup, dim3(1), dim3(NT), 0, st, p, sc.ticket, sc.err);
+    if (ntasks > 0) {
+        const int grid = (int)std::min<int64_t>(ntasks, P2_WG_PER_CU * (int64_t)di.cus);
+        LAUNCH(STILES_TK_PHASE2, k_phase2, dim3(grid), dim3(NT), 0, st, p, sc);
+    }
+    LAUNCH(STILES_TK_OTHER, k_selinv_final, dim3(1), dim3(64), 0, st, (const int*)v.winfo, (const int*)v.err,
+           (int*)info);
+    return 0;
+}
+
 int stiles_selinv(const double* Lm, double* S, int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile,
                   int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
     stiles_layout lay;
@@ -1738,46 +1819,34 @@ int stiles_selinv(const double* Lm, double* S, int64_t n, int64_t bandwidth, int
     if (!S || S == Lm) return -2;
     if (!info) return -7;
     if (!workspace || workspace_bytes < stiles_selinv_workspace_bytes(&lay)) return -8;
-    hipStream_t st = S_(stream);
-    Lay L = to_dev(lay);
-    const SelinvWs v = selinv_ws(L, (char*)workspace);
-    const int nb64 = L.b / 64, nab = arrow_blocks(L.ap);
-    const int64_t ntasks = p2_total_tasks(L);
-    if (ntasks > 0x7fffffff) return -3;
+    return selinv_impl(Lm, S, lay, 0, info, workspace, S_(stream));
+}
 
-    LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, v.winfo, 0);
-    if (L.bt > 0) {
-        const int64_t tail = (int64_t)L.bt * (L.bt + 1) / 2 * L.b * L.b;
-        LAUNCH(STILES_TK_OTHER, k_zero_unused, dim3(grid_for(tail)), dim3(NT), 0, st, S, L);
-    }
-    // Phase 1
-    LAUNCH(STILES_TK_PHASE1, k_trtri_all, dim3((unsigned)(L.nt + (L.ap > 0))), dim3(NT), 0, st, Lm, v.W, L, v.winfo);
-    {
-        const int64_t g = L.nt * (int64_t)(L.bt * nb64 + nab) * nb64;
-        if (g > 0) {
-            LAUNCH(STILES_TK_PHASE1, k_trmm_all, dim3((unsigned)g), dim3(NT), 0, st, Lm, v.W, L);
-        }
-    }
-    {
-        const int64_t g = (L.nt + (L.ap > 0)) * (int64_t)lauum_per(L);
-        LAUNCH(STILES_TK_PHASE1, k_lauum_all, dim3((unsigned)g), dim3(NT), 0, st, (const double*)v.W, S, L);
-    }
-    // Phase 2, bottom-right to top-left, one persistent launch
-    {
-        DevInfo di;
-        if (dev_info(&di)) return STILES_EHIP;
-        const P2 p = make_p2(S, v, L, (int)ntasks);
-        Sched sc;
-        sc.ticket = v.ticket;
-        sc.err = v.err;
-        sc.spin_limit = spin_limit_ticks(di);
-        sc.withhold = debug_withhold();
-        LAUNCH(STILES_TK_OTHER, k_p2_setup, dim3(1), dim3(NT), 0, st, p, sc.ticket, sc.err);
-        const int grid = (int)std::min<int64_t>(ntasks, P2_WG_PER_CU * (int64_t)di.cus);
-        LAUNCH(STILES_TK_PHASE2, k_phase2, dim3(grid), dim3(NT), 0, st, p, sc);
-    }
-    LAUNCH(STILES_TK_OTHER, k_selinv_final, dim3(1), dim3(64), 0, st, (const int*)v.winfo, (const int*)v.err,
-           (int*)info);
+int stiles_selinv_range(const double* Lm, double* S, int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile,
+                        int64_t first_column, int32_t* info, void* workspace, size_t workspace_bytes, void* stream) {
+    stiles_layout lay;
+    int rc = make_layout(n, bandwidth, arrow, tile, &lay);
+    if (rc) return rc - 2;
+    if (!Lm) return -1;
+    if (!S || S == Lm) return -2;
+    if (first_column < 0 || first_column > lay.nt) return -7;
+    if (!info) return -8;
+    if (!workspace || workspace_bytes < stiles_selinv_workspace_bytes(&lay)) return -9;
+    return selinv_impl(Lm, S, lay, first_column, info, workspace, S_(stream));
+}
+
+int stiles_gather(const double* Sigma, int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile, const int64_t* ij,
+                  int64_t count, double* out, void* stream) {
+    stiles_layout lay;
+    int rc = make_layout(n, bandwidth, arrow, tile, &lay);
+    if (rc) return rc - 1;
+    if (!Sigma) return -1;
+    if (count < 0) return -7;
+    if (count == 0) return 0;
+    if (!ij) return -6;
+    if (!out) return -8;
+    LAUNCH(STILES_TK_OTHER, k_gather, dim3(grid_for(count)), dim3(NT), 0, S_(stream), Sigma, to_dev(lay), ij, count,
+           out);
     return 0;
 }
 
@@ -1812,10 +1881,11 @@ int stiles_inverse(const double* Lm, double* Ainv, int64_t n, int64_t bandwidth,
     LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, v.err, 0);
     LAUNCH(STILES_TK_OTHER, k_zero_ints, dim3(grid_for(np * np * 2)), dim3(NT), 0, st, (int*)D, np * np * 2);
     // Phase 1: X_J, Lhat (as for stiles_selinv)
-    LAUNCH(STILES_TK_PHASE1, k_trtri_all, dim3((unsigned)(L.nt + (L.ap > 0))), dim3(NT), 0, st, Lm, v.W, L, v.winfo);
+    LAUNCH(STILES_TK_PHASE1, k_trtri_all, dim3((unsigned)(L.nt + (L.ap > 0))), dim3(NT), 0, st, Lm, v.W, L, v.winfo,
+           (int64_t)0);
     {
         const int64_t g = L.nt * (int64_t)(L.bt * nb64 + nab) * nb64;
-        if (g > 0) LAUNCH(STILES_TK_PHASE1, k_trmm_all, dim3((unsigned)g), dim3(NT), 0, st, Lm, v.W, L);
+        if (g > 0) LAUNCH(STILES_TK_PHASE1, k_trmm_all, dim3((unsigned)g), dim3(NT), 0, st, Lm, v.W, L, (int64_t)0);
     }
     LAUNCH(STILES_TK_PHASE1, k_inv_lauum, dim3((unsigned)((L.nt + (L.ap > 0)) * (int64_t)lauum_per(L))), dim3(NT), 0,
            st, (const double*)v.W, D, np, L);

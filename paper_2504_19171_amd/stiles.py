@@ -42,6 +42,8 @@ EXPORTED = (
     "stiles_trace_product",
     "stiles_inverse_workspace_bytes",
     "stiles_inverse",
+    "stiles_selinv_range",
+    "stiles_gather",
 )
 
 TIMING_KINDS = ("potrf", "trsm", "update", "phase1", "phase2", "factor", "other")
@@ -108,6 +110,10 @@ def load(path: Optional[str] = None):
     lib.stiles_inverse_workspace_bytes.restype = _sz
     lib.stiles_inverse.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _sz, _vp]
     lib.stiles_inverse.restype = ctypes.c_int
+    lib.stiles_selinv_range.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, _i64, _vp, _vp, _sz, _vp]
+    lib.stiles_selinv_range.restype = ctypes.c_int
+    lib.stiles_gather.argtypes = [_vp, _i64, _i64, _i64, _i32, _vp, _i64, _vp, _vp]
+    lib.stiles_gather.restype = ctypes.c_int
     lib.stiles_trace_workspace_bytes.argtypes = []
     lib.stiles_trace_workspace_bytes.restype = _sz
     lib.stiles_trace_product.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _sz, _vp]
@@ -364,3 +370,71 @@ def inverse(L, lay: Layout, out=None, workspace=None, stream=None):
     if rc != 0:
         raise StilesError(rc, "stiles_inverse")
     return Ainv, info
+
+
+def selinv_range(L, lay: Layout, first_column: int, out=None, workspace=None, stream=None):
+    """:func:`selinv` restricted to the tile columns >= first_column (and the corner)."""
+    import torch
+    L = _dev_f64(L, "L")
+    S = out if out is not None else torch.empty_like(L)
+    ws = workspace if workspace is not None else torch.empty(lay.selinv_workspace_bytes, dtype=torch.uint8,
+                                                             device=L.device)
+    info = torch.empty(1, dtype=torch.int32, device=L.device)
+    rc = load().stiles_selinv_range(L.data_ptr(), S.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                                    int(first_column), info.data_ptr(), ws.data_ptr(), ws.numel(),
+                                    _stream_handle(stream))
+    if rc != 0:
+        raise StilesError(rc, "stiles_selinv_range")
+    return S, info
+
+
+def gather(Sigma, lay: Layout, ij, out=None, stream=None):
+    """Sigma(i, j) for the pairs ij (a (k, 2) int64 device tensor) read off the tile layout."""
+    import torch
+    Sigma = _dev_f64(Sigma, "Sigma")
+    ij = ij.contiguous()
+    if ij.dtype != torch.int64 or not ij.is_cuda or ij.dim() != 2 or ij.shape[1] != 2:
+        raise TypeError("ij must be a (k, 2) int64 CUDA tensor")
+    k = ij.shape[0]
+    if out is None:
+        out = torch.empty(k, dtype=torch.float64, device=Sigma.device)
+    rc = load().stiles_gather(Sigma.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                              ij.data_ptr() if k else None, k, out.data_ptr() if k else None, _stream_handle(stream))
+    if rc != 0:
+        raise StilesError(rc, "stiles_gather")
+    return out
+
+
+def selection_closure(lay: Layout, pairs):
+    """Host side of a selection (Sec. III-B): for pairs (i, j) -> (whether every
+    pair lies in the tile pattern of L, the first tile column of the closure).
+    In the pattern, the closure runs from the leftmost selected tile column to
+    the last (the corner alone is column N)."""
+    import numpy as np
+    p = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
+    hi = np.maximum(p[:, 0], p[:, 1])
+    lo = np.minimum(p[:, 0], p[:, 1])
+    if p.size and (lo.min() < 0 or hi.max() >= lay.n):
+        raise ValueError("pair outside the matrix")
+    b, nb = lay.tile, lay.nb
+    band = hi < nb
+    inside = np.ones(len(p), dtype=bool)
+    inside[band] = (hi[band] // b - lo[band] // b) <= lay.bt
+    col = np.where(lo < nb, lo // b, lay.nt)
+    first = int(col.min()) if len(p) else lay.nt
+    return bool(inside.all()), first
+
+
+def select(L, lay: Layout, pairs, stream=None):
+    """Sigma(i, j) for a list of pairs: when they all lie in the tile pattern of L,
+    the selected inverse of their closure only (stiles_selinv_range) read with
+    stiles_gather; otherwise the full inverse.  Returns (values, info) on the device."""
+    import numpy as np
+    import torch
+    inside, first = selection_closure(lay, pairs)
+    ij = torch.as_tensor(np.asarray(pairs, dtype=np.int64).reshape(-1, 2), device=L.device)
+    if inside:
+        S, info = selinv_range(L, lay, first, stream=stream)
+        return gather(S, lay, ij, stream=stream), info
+    X, info = inverse(L, lay, stream=stream)
+    return X.t()[ij[:, 0], ij[:, 1]], info

@@ -148,3 +148,35 @@ def test_host_pack_roundtrip(nb, w, a, b):
     pad = full[r0:, r0:]
     np.testing.assert_array_equal(pad, np.eye(b - r0))
     assert np.all(full[r0:, :r0] == 0) and np.all(full[:r0, r0:] == 0)
+
+
+def test_selection_closure():
+    """Selected pairs -> (all in L's tile pattern?, first tile column of the closure)."""
+    lay = st.layout(1020, 100, 20, 64)      # nb = 1000, N = 16, B = 2
+    assert (lay.nt, lay.bt) == (16, 2)
+    assert st.selection_closure(lay, [(10, 5)]) == (True, 0)
+    assert st.selection_closure(lay, [(500, 400)]) == (True, 6)        # tiles 7 and 6
+    assert st.selection_closure(lay, [(400, 500)]) == (True, 6)        # either order
+    assert st.selection_closure(lay, [(900, 100)])[0] is False          # 13 tiles apart
+    assert st.selection_closure(lay, [(1005, 300)]) == (True, 4)       # arrow row
+    assert st.selection_closure(lay, [(1010, 1003)]) == (True, 16)     # the corner alone
+    assert st.selection_closure(lay, [(1010, 1003), (700, 650)]) == (True, 10)
+    with pytest.raises(ValueError):
+        st.selection_closure(lay, [(1020, 3)])
+
+
+def test_selection_entry_points_reject_bad_arguments_before_any_gpu_call():
+    lib = st.load()
+    lay = st.layout(100, 4, 3, 64)
+    wss = lay.selinv_workspace_bytes
+    assert lib.stiles_selinv_range(None, 16, 100, 4, 3, 64, 0, 8, 8, wss, None) == -1
+    assert lib.stiles_selinv_range(8, 8, 100, 4, 3, 64, 0, 8, 8, wss, None) == -2
+    assert lib.stiles_selinv_range(8, 16, 100, 4, 3, 64, -1, 8, 8, wss, None) == -7
+    assert lib.stiles_selinv_range(8, 16, 100, 4, 3, 64, lay.nt + 1, 8, 8, wss, None) == -7
+    assert lib.stiles_selinv_range(8, 16, 100, 4, 3, 64, 0, None, 8, wss, None) == -8
+    assert lib.stiles_selinv_range(8, 16, 100, 4, 3, 64, 0, 8, 8, wss - 1, None) == -9
+    assert lib.stiles_gather(None, 100, 4, 3, 64, 8, 1, 8, None) == -1
+    assert lib.stiles_gather(8, 100, 4, 3, 64, None, 1, 8, None) == -6
+    assert lib.stiles_gather(8, 100, 4, 3, 64, 8, -1, 8, None) == -7
+    assert lib.stiles_gather(8, 100, 4, 3, 64, 8, 1, None, None) == -8
+    assert lib.stiles_gather(8, 100, 4, 3, 64, None, 0, None, None) == 0
