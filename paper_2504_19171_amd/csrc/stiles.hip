@@ -69,38 +69,51 @@ __global__ void k_set_int(int* p, int v) {
 }
 
 // Pack the canonical band form into the tile layout (every double written).
+// Workgroup g < N (B+1) writes band tile g = J (B+1) + d, i.e. tile (J+d, J);
+// the next N write the arrow tiles J; the last one the corner.  In a band tile
+// thread r writes row r of every column (consecutive threads, consecutive
+// addresses); the tile indices are uniform, so no division per element.
 __global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, const double* __restrict__ P,
                                             const double* __restrict__ C, double* __restrict__ T, Lay L) {
-    const int64_t b = L.b, b2 = b * b;
-    for (int64_t idx = blockIdx.x * (int64_t)NT + threadIdx.x; idx < L.total;
-         idx += (int64_t)gridDim.x * NT) {
-        double v = 0.0;
-        if (idx < L.off_arrow) {
-            const int64_t t = idx / b2, e = idx % b2;
-            const int64_t J = t / (L.bt + 1), d = t % (L.bt + 1);
-            const int64_t r = e % b, c = e / b;
-            const int64_t i = (J + d) * b + r, j = J * b + c;
-            if (J + d < L.nt) {
-                if (i < L.nb && j < L.nb) {
-                    const int64_t hi = i > j ? i : j, lo = i > j ? j : i;
-                    if (hi - lo <= L.w) v = ab[(hi - lo) * L.nb + lo];
-                } else if (i == j) {
-                    v = 1.0;
+    const int64_t b = L.b;
+    const int64_t nband = L.nt * (int64_t)(L.bt + 1);
+    const int64_t g = blockIdx.x;
+    if (g < nband) {
+        const int64_t J = g / (L.bt + 1), d = g % (L.bt + 1);
+        double* O = T + g * b * b;
+        const bool live = J + d < L.nt;
+        for (int r = threadIdx.x; r < b; r += NT) {
+            const int64_t i = (J + d) * b + r;
+            for (int c = 0; c < b; ++c) {
+                const int64_t j = J * b + c;
+                double v = 0.0;
+                if (live) {
+                    if (i < L.nb && j < L.nb) {
+                        const int64_t k = i >= j ? i - j : j - i, lo = i >= j ? j : i;
+                        if (k <= L.w) v = ab[k * L.nb + lo];
+                    } else if (i == j) {
+                        v = 1.0;
+                    }
                 }
+                O[r + c * b] = v;
             }
-        } else if (idx < L.off_corner) {
-            const int64_t e = idx - L.off_arrow;
-            const int64_t J = e / ((int64_t)L.ap * b), f = e % ((int64_t)L.ap * b);
-            const int64_t r = f % L.ap, c = f / L.ap;
-            const int64_t j = J * b + c;
-            if (r < L.a && j < L.nb) v = P[r * L.nb + j];
-        } else {
-            const int64_t e = idx - L.off_corner;
-            const int64_t r = e % L.ap, c = e / L.ap;
-            if (r < L.a && c < L.a) v = C[r * L.a + c];
-            else if (r == c) v = 1.0;
         }
-        T[idx] = v;
+    } else if (g < nband + L.nt) {
+        const int64_t J = g - nband;
+        double* O = T + L.arrow(J);
+        const int ap = L.ap;
+        for (int e = threadIdx.x; e < ap * (int)b; e += NT) {
+            const int r = e % ap, c = e / ap;
+            const int64_t j = J * b + c;
+            O[e] = (r < L.a && j < L.nb) ? P[r * L.nb + j] : 0.0;
+        }
+    } else {
+        double* O = T + L.corner();
+        const int ap = L.ap;
+        for (int e = threadIdx.x; e < ap * ap; e += NT) {
+            const int r = e % ap, c = e / ap;
+            O[e] = (r < L.a && c < L.a) ? C[r * L.a + c] : (r == c ? 1.0 : 0.0);
+        }
     }
 }
 
@@ -1706,8 +1719,8 @@ int stiles_pack(const double* ab, const double* arrow_rows, const double* corner
     if (arrow > 0 && !corner) return -3;
     if (!tiles) return -4;
     Lay L = to_dev(lay);
-    LAUNCH(STILES_TK_OTHER, k_pack, dim3(grid_for(L.total)), dim3(NT), 0, S_(stream), ab, arrow_rows, corner,
-                       tiles, L);
+    LAUNCH(STILES_TK_OTHER, k_pack, dim3((unsigned)(L.nt * (int64_t)(L.bt + 1) + L.nt + 1)), dim3(NT), 0, S_(stream),
+           ab, arrow_rows, corner, tiles, L);
     return 0;
 }
 
