@@ -34,6 +34,7 @@ struct Lay {
 __host__ __device__ inline int arrow_blocks(int ap) { return (ap + 63) / 64; }
 __host__ __device__ inline int imin_(int x, int y) { return x < y ? x : y; }
 __host__ __device__ inline int imax_(int x, int y) { return x > y ? x : y; }
+__host__ __device__ inline int64_t imax64(int64_t x, int64_t y) { return x > y ? x : y; }
 
 // The same pointer in every lane, held in scalar registers: lets loads use a
 // scalar base plus a 32-bit per-lane offset instead of 64-bit addresses.

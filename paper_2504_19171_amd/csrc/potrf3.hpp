@@ -346,7 +346,7 @@ __device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& s
 #pragma unroll
     for (int q = 0; q < NS; ++q)
 #pragma unroll
-        for (int r = 0; r < 4; ++r) nxt[S0 + q][r] = ld_s(Mc, (uint32_t)((16 * Is[q] + li) + (c2 + 4 * r + lk) * ldi));
+        for (int r = 0; r < 4; ++r) nxt[S0 + q][r] = ld_coh_s(Mc, (uint32_t)((16 * Is[q] + li) + (c2 + 4 * r + lk) * ldi));
     dbl4 red[NS];
 #pragma unroll
     for (int q = 0; q < NS; ++q) red[q] = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -407,6 +407,8 @@ __device__ __forceinline__ void p3_update_dispatch(int s0, dbl4 (&nxt)[P3_SLOTS]
     }
 }
 
+// The raw tiles are read with device-coherent loads: in the single-launch
+// factor the previous tile column's updates are other workgroups' stores.
 // In-place Cholesky of the m x m lower triangle of M (column-major, leading
 // dimension ld), m a multiple of 64, m <= 256; zeros go only into the upper
 // parts of the diagonal 16 x 16 blocks (the rest of the strict upper triangle
@@ -459,12 +461,12 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
         const int q = threadIdx.x, r = q >> 6, ln = q & 63;
 #pragma unroll
         for (int I = 0; I < 16; ++I)
-            v[I] = ld_s(Mc, (uint32_t)((16 * imin_(I, np - 1) + (ln & 15)) + (4 * r + (ln >> 4)) * ldi));
+            v[I] = ld_coh_s(Mc, (uint32_t)((16 * imin_(I, np - 1) + (ln & 15)) + (4 * r + (ln >> 4)) * ldi));
 #pragma unroll
         for (int I = 1; I < 16; ++I)
             if (I < np) sm.pool[p3_slot(tab, I, 0)][q] = v[I];
         const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
-        sm.D[j * P3_LD + i] = ld_s(Mc, (uint32_t)(i + j * ldi));
+        sm.D[j * P3_LD + i] = ld_coh_s(Mc, (uint32_t)(i + j * ldi));
     }
     for (int e = threadIdx.x; e < 2 * 16 * P3_LD; e += 256) sm.Y[0][e] = 0.0;
     // panel wavefronts w = 1..P3_PW own the row tiles I = P3_PW s + w >= 1 of every panel
@@ -476,7 +478,7 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
         for (int s = 0; s < P3_SLOTS; ++s) {
             const int I = imin_(P3_PW * s + w, np - 1);
 #pragma unroll
-            for (int r = 0; r < 4; ++r) nxt[s][r] = ld_s(Mc, (uint32_t)((16 * I + li) + (16 + 4 * r + lk) * ldi));
+            for (int r = 0; r < 4; ++r) nxt[s][r] = ld_coh_s(Mc, (uint32_t)((16 * I + li) + (16 + 4 * r + lk) * ldi));
         }
         if (w == 1) {
 #pragma unroll

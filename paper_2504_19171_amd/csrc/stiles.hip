@@ -244,7 +244,7 @@ __device__ inline bool tr_panel(double* C, int ld, const double* Ljj, const doub
     double acur[4][4], anext[4][4];
     dbl4 cn;
 #pragma unroll
-    for (int r = 0; r < 4; ++r) cn[r] = ld_s(C, (uint32_t)(li + (4 * r + lk) * ld));
+    for (int r = 0; r < 4; ++r) cn[r] = coh ? ld_coh_s(C, (uint32_t)(li + (4 * r + lk) * ld)) : ld_s(C, (uint32_t)(li + (4 * r + lk) * ld));
 #pragma unroll
     for (int t = 0; t < 4; ++t)
 #pragma unroll
@@ -264,7 +264,10 @@ __device__ inline bool tr_panel(double* C, int ld, const double* Ljj, const doub
         fetchA(anext, pn);
         dbl4 cnext;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) cnext[r] = ld_s(C, (uint32_t)(li + (16 * pn + 4 * r + lk) * ld));
+        for (int r = 0; r < 4; ++r) {
+            const uint32_t ci = (uint32_t)(li + (16 * pn + 4 * r + lk) * ld);
+            cnext[r] = coh ? ld_coh_s(C, ci) : ld_s(C, ci);
+        }
         // this wavefront's part of Z_p^T (wavefronts past the fourth, if the
         // workgroup has them, only keep the barriers)
         if (w < 4) {
@@ -340,7 +343,31 @@ struct UpBlock {
     int rows_a, rows_b;   // valid rows from the block's first row on (<= 64)
     int ga, gb;           // TRSM row blocks (16 rows) of the first rows of A and B
     int diag;             // a diagonal block of a symmetric target: lower part only
+    int* cnt;             // single-launch factor: updates applied to the target so far (else nullptr)
+    int before;           // ... and how many come before this one
 };
+
+// Single-launch factor: per 64 x 64 target block, the number of tile columns
+// whose update of it is done.  Band tile (K+d, K), block (i, j); arrow tile
+// K, block (i, j); corner block (i, j).  Tile (I, K) of the band is updated
+// by the columns max(0, I - B) .. K - 1, arrow tile K by max(0, K - B) ..
+// K - 1, the corner by every column.
+__host__ __device__ inline int64_t upd_band(const Lay& L, int64_t K, int d, int i, int j) {
+    const int C64 = L.b / 64;
+    return ((K * (L.bt + 1) + d) * C64 + i) * C64 + j;
+}
+__host__ __device__ inline int64_t upd_arrow(const Lay& L, int64_t K, int i, int j) {
+    const int C64 = L.b / 64, na = (L.ap + 63) / 64;
+    return L.nt * (int64_t)(L.bt + 1) * C64 * C64 + (K * na + i) * C64 + j;
+}
+__host__ __device__ inline int64_t upd_corner(const Lay& L, int i, int j) {
+    const int C64 = L.b / 64, na = (L.ap + 63) / 64;
+    return L.nt * (int64_t)(L.bt + 1) * C64 * C64 + L.nt * (int64_t)na * C64 + (int64_t)i * na + j;
+}
+__host__ __device__ inline int64_t upd_ints(const Lay& L) {
+    const int na = (L.ap + 63) / 64;
+    return upd_corner(L, 0, 0) + (int64_t)na * na;
+}
 __host__ __device__ inline int col_up_blocks(const Lay& L, int64_t J) {
     const int C64 = L.b / 64, s = L.s(J), na = (L.ap + 63) / 64;
     int cnt = 0;
@@ -349,9 +376,11 @@ __host__ __device__ inline int col_up_blocks(const Lay& L, int64_t J) {
     if (L.ap > 0) cnt += s * na * C64 + na * (na + 1) / 2;
     return cnt;
 }
-__device__ inline UpBlock col_up_decode(double* Lm, const Lay& L, int64_t J, int t) {
+__device__ inline UpBlock col_up_decode(double* Lm, const Lay& L, int64_t J, int t, int* upd) {
     const int C64 = L.b / 64, s = L.s(J), na = (L.ap + 63) / 64, nbr = L.b / 16, b = L.b;
     UpBlock u;
+    u.cnt = nullptr;
+    u.before = 0;
     for (int d = 1; d <= s; ++d) {
         for (int e = 1; e <= d; ++e) {
             const int cnt = (d == e) ? C64 * (C64 + 1) / 2 : C64 * C64;
@@ -363,6 +392,10 @@ __device__ inline UpBlock col_up_decode(double* Lm, const Lay& L, int64_t J, int
                 u.B = Lm + L.band(J, e) + 64 * j; u.ldb = b; u.rows_b = 64; u.gb = (e - 1) * nbr + 4 * j;
                 u.O = Lm + L.band(J + e, d - e) + 64 * i + (int64_t)64 * j * b; u.ldo = b;
                 u.diag = (d == e && i == j);
+                if (upd) {
+                    u.cnt = upd + upd_band(L, J + e, d - e, i, j);
+                    u.before = (int)(J - imax64(0, J + d - L.bt));
+                }
                 return u;
             }
             t -= cnt;
@@ -375,6 +408,10 @@ __device__ inline UpBlock col_up_decode(double* Lm, const Lay& L, int64_t J, int
         u.B = Lm + L.band(J, e) + 64 * j; u.ldb = b; u.rows_b = 64; u.gb = (e - 1) * nbr + 4 * j;
         u.O = Lm + L.arrow(J + e) + 64 * i + (int64_t)64 * j * L.ap; u.ldo = L.ap;
         u.diag = 0;
+        if (upd) {
+            u.cnt = upd + upd_arrow(L, J + e, i, j);
+            u.before = (int)(J - imax64(0, J + e - L.bt));
+        }
         return u;
     }
     t -= s * na * C64;
@@ -384,6 +421,10 @@ __device__ inline UpBlock col_up_decode(double* Lm, const Lay& L, int64_t J, int
     u.B = Lm + L.arrow(J) + 64 * j; u.ldb = L.ap; u.rows_b = imin_(64, L.ap - 64 * j); u.gb = ga0 + 4 * j;
     u.O = Lm + L.corner() + 64 * i + (int64_t)64 * j * L.ap; u.ldo = L.ap;
     u.diag = (i == j);
+    if (upd) {
+        u.cnt = upd + upd_corner(L, i, j);
+        u.before = (int)J;
+    }
     return u;
 }
 
@@ -435,6 +476,9 @@ __device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, cons
     }
     dbl4 acc[2][2];
     double ov[2][2][4];
+    // the target as the earlier tile columns left it (device-coherent: in the
+    // single-launch factor they are other workgroups of the same kernel)
+    if (u.cnt && u.before > 0 && !sched_wait(sc, u.cnt, u.before, sh)) return false;
 #pragma unroll
     for (int x = 0; x < 2; ++x)
 #pragma unroll
@@ -442,7 +486,7 @@ __device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, cons
             acc[x][y] = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int r = 0; r < 4; ++r)
-                ov[x][y][r] = ld_s(O, (uint32_t)((16 * ra[x] + li) + (16 * rb[y] + 4 * r + lk) * u.ldo));
+                ov[x][y][r] = ld_coh_s(O, (uint32_t)((16 * ra[x] + li) + (16 * rb[y] + 4 * r + lk) * u.ldo));
         }
     // the operands of panel p + 1 are loaded (once its TRSM steps are
     // announced) while panel p is multiplied
@@ -489,9 +533,10 @@ __device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, cons
             if (ti < ta && tj < tb && !(u.diag && ti < tj)) {
 #pragma unroll
                 for (int r = 0; r < 4; ++r)
-                    st_s(O, (uint32_t)((16 * ti + li) + (16 * tj + 4 * r + lk) * u.ldo), ov[x][y][r] - acc[x][y][r]);
+                    st_coh_s(O, (uint32_t)((16 * ti + li) + (16 * tj + 4 * r + lk) * u.ldo), ov[x][y][r] - acc[x][y][r]);
             }
         }
+    if (u.cnt) sched_signal(sc, u.cnt, 0);   // waits for the stores, then a barrier
     return true;
 }
 
@@ -504,14 +549,23 @@ union ColSmem {
     TrSmem tr;
 };
 // Task t of tile column J; false when the kernel must stop (a wait failed).
+// upd (single-launch factor, else nullptr): the POTRF waits until the
+// earlier columns' updates of its tile are in, a TRSM block until those of
+// its rows are; the update blocks wait for the earlier updates of their
+// targets (col_update).
 __device__ inline bool col_task(ColSmem& sm, int& sh, double* Lm, const Lay& L, int64_t J, double* Yd, int* cf,
-                                const Sched& st, double* ldp, int* info, int t) {
+                                const Sched& st, double* ldp, int* info, int t, int* upd) {
     const int ntr = col_tr_blocks(L, J);
-    const int nbr = L.b / 16, s = L.s(J);
+    const int nbr = L.b / 16, s = L.s(J), C64 = L.b / 64;
     int* fpo = cf + CF_PO;
     int* ftr = cf + CF_TR;
     {
         if (t == 0) {
+            if (upd) {
+                const int need = (int)(J - imax64(0, J - L.bt));
+                for (int i = 0; i < C64 && need > 0; ++i)
+                    if (!col_wait(st, upd + upd_band(L, J, 0, i, 0), i + 1, need, &sh)) return false;
+            }
             int fail;
             double ls, lc;
             potrf3(Lm + L.band(J, 0), L.b, L.b, Yd, sm.po, &fail, &ls, &lc, fpo);
@@ -526,30 +580,66 @@ __device__ inline bool col_task(ColSmem& sm, int& sh, double* Lm, const Lay& L, 
             int ld;
             if (g < s * nbr) { C = Lm + L.band(J, 1 + g / nbr) + (g % nbr) * 16; ld = L.b; }
             else { C = Lm + L.arrow(J) + (g - s * nbr) * 16; ld = L.ap; }
+            if (upd) {
+                bool ok = true;
+                if (g < s * nbr) {
+                    const int d = 1 + g / nbr;
+                    const int need = (int)(J - imax64(0, J + d - L.bt));
+                    if (need > 0) ok = col_wait(st, upd + upd_band(L, J, d, (g % nbr) / 4, 0), C64, need, &sh);
+                } else {
+                    const int need = (int)(J - imax64(0, J - L.bt));
+                    if (need > 0) ok = col_wait(st, upd + upd_arrow(L, J, (g - s * nbr) / 4, 0), C64, need, &sh);
+                }
+                if (!ok) return false;
+            }
             if (!tr_panel(C, ld, Lm + L.band(J, 0), Yd, L.b, fpo, ftr + g, st, sm.tr)) return false;
         } else {
-            const UpBlock u = col_up_decode(Lm, L, J, t - 1 - ntr);
+            const UpBlock u = col_up_decode(Lm, L, J, t - 1 - ntr, upd);
             if (!col_update(u, ftr, L.b / 16, st, &sh)) return false;
         }
     }
     return true;
 }
-__device__ inline void col_run(ColSmem& sm, int& sh, double* Lm, const Lay& L, int64_t J, double* Yd, int* cf,
-                               const Sched& sc, double* ldp, int* info) {
-    const int ntasks = 1 + col_tr_blocks(L, J) + col_up_blocks(L, J);
-    Sched st = sc;
-    st.ticket = cf + CF_TICKET;
-    for (;;) {
-        const int t = sched_next(st, ntasks, &sh);
-        if (t < 0) return;
-        if (!col_task(sm, sh, Lm, L, J, Yd, cf, st, ldp, info, t)) return;
-    }
-}
-__global__ __launch_bounds__(P3_NT) void k_column(double* Lm, Lay L, int64_t J, double* Yd, int* cf, Sched sc,
-                                               double* ldp, int* info) {
+// The whole factor of the band tile columns in one persistent launch.
+// Ticket g is task g - off[J] of tile column J (off: first ticket of each
+// column, off[N] = all), so the tasks go column by column and, inside a
+// column, in the order above: every wait is for a smaller ticket, and the
+// launch cannot deadlock however many workgroups are resident.  Across
+// columns the tasks wait on the update counters (col_task): the POTRF of
+// column J+1 starts as soon as column J's updates of its tile are in, while
+// the rest of column J's trailing update goes on.
+__global__ __launch_bounds__(P3_NT) void k_factor_all(double* Lm, Lay L, double* Yd, int* cf, int* upd, const int* off,
+                                                   Sched sc, double* ldp, int* info) {
     __shared__ ColSmem sm;
     __shared__ int sh;
-    col_run(sm, sh, Lm, L, J, Yd, cf, sc, ldp, info);
+    const int64_t N = L.nt;
+    const int ntot = off[N];
+    const int cstride = col_stride(L);
+    for (;;) {
+        const int g = sched_next(sc, ntot, &sh);
+        if (g < 0) return;
+        int lo = 0, hi = (int)N;
+        while (hi - lo > 1) {
+            const int mid = (lo + hi) >> 1;
+            if (off[mid] <= g) lo = mid; else hi = mid;
+        }
+        const int64_t J = lo;
+        if (!col_task(sm, sh, Lm, L, J, Yd + J * (int64_t)L.b * 16, cf + J * cstride, sc, ldp + 2 * J, info,
+                      g - off[J], upd))
+            return;
+    }
+}
+
+// First ticket of every tile column (off[N] = all tickets), and the ticket counter.
+__global__ void k_factor_offsets(Lay L, int* off, int* ticket) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    int acc = 0;
+    for (int64_t J = 0; J < L.nt; ++J) {
+        off[J] = acc;
+        acc += 1 + col_tr_blocks(L, J) + col_up_blocks(L, J);
+    }
+    off[L.nt] = acc;
+    *ticket = 0;
 }
 
 // C (rows x rows, lower blocks) -= P P^T, P rows x K (generic, corner blocking).
@@ -1013,6 +1103,9 @@ struct FactorWs {
     double* Xc;     // 256 x 256 inverse of the blocked corner
     double* Yd;     // 16 x 16 diagonal-block inverses of every L_JJ
     int* cf;        // per tile column counters
+    int* upd;       // update counters of the single-launch factor (upd_ints)
+    int* off;       // first ticket of every tile column (N + 1)
+    int* ticket;
 };
 __host__ __device__ inline FactorWs factor_ws(const Lay& L, char* ws) {
     FactorWs f;
@@ -1022,6 +1115,9 @@ __host__ __device__ inline FactorWs factor_ws(const Lay& L, char* ws) {
     f.Xc = f.ldp + 2 * (L.nt + 2);
     f.Yd = f.Xc + 256 * 256;
     f.cf = (int*)(f.Yd + L.nt * (int64_t)L.b * 16);
+    f.upd = f.cf + L.nt * (int64_t)col_stride(L);
+    f.off = f.upd + upd_ints(L);
+    f.ticket = f.winfo + 32;
     return f;
 }
 
@@ -1143,7 +1239,7 @@ __global__ __launch_bounds__(P3_NT) void kb_column(BColArgs a, int64_t J) {
         const BInst& I = a.bi[a.order[g - a.off[t]]];
         const FactorWs f = factor_ws(I.L, I.ws);
         if (!col_task(sm, sh, I.Lm, I.L, J, f.Yd + J * (int64_t)I.L.b * 16, f.cf + J * col_stride(I.L), sc,
-                      f.ldp + 2 * J, f.winfo, t))
+                      f.ldp + 2 * J, f.winfo, t, nullptr))
             return;
     }
 }
@@ -1575,7 +1671,7 @@ static size_t fws_bytes(const stiles_layout& l) {
     const Lay L = to_dev(l);
     return WS_HEAD + sizeof(double) * (size_t)(2 * (l.nt + 2)) +
            sizeof(double) * (size_t)(256 * 256 + l.nt * (int64_t)l.tile * 16) +
-           sizeof(int) * (size_t)(l.nt * (int64_t)col_stride(L));
+           sizeof(int) * (size_t)(l.nt * (int64_t)col_stride(L) + upd_ints(L) + l.nt + 1);
 }
 // selinv workspace (SelinvWs): head (info, ticket, error words), the Phase 1
 // tiles (inverted diagonal tiles, Lhat, corner inverse) in the tile layout,
@@ -1737,7 +1833,6 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     hipStream_t st = S_(stream);
     Lay L = to_dev(lay);
     const FactorWs f = factor_ws(L, (char*)workspace);
-    const int64_t y_per = (int64_t)L.b * 16;
     const int cstride = col_stride(L);
     DevInfo di;
     if (dev_info(&di)) return STILES_EHIP;
@@ -1754,16 +1849,19 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     }
     LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, f.winfo, 0x7fffffff);
     LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, f.err, 0);
-    LAUNCH(STILES_TK_OTHER, k_zero_ints, dim3(grid_for(L.nt * (int64_t)cstride)), dim3(NT), 0, st, f.cf,
-           L.nt * (int64_t)cstride);
-    // One launch per tile column, in order: POTRF of the diagonal tile, the
-    // panel TRSM below it and the trailing updates run as concurrent tasks of
-    // that launch, pipelined on the 16-column panels (k_column).
-    for (int64_t J = 0; J < L.nt; ++J) {
-        const int ntasks = 1 + col_tr_blocks(L, J) + col_up_blocks(L, J);
-        LAUNCH(STILES_TK_FACTOR, k_column, dim3((unsigned)std::min(ntasks, di.cus)), dim3(P3_NT), 0, st, Lm, L, J,
-               f.Yd + J * y_per, f.cf + J * cstride, sc, f.ldp + 2 * J, f.winfo);
-    }
+    LAUNCH(STILES_TK_OTHER, k_zero_ints, dim3(grid_for(L.nt * (int64_t)cstride + upd_ints(L))), dim3(NT), 0, st,
+           f.cf, L.nt * (int64_t)cstride + upd_ints(L));
+    LAUNCH(STILES_TK_OTHER, k_factor_offsets, dim3(1), dim3(64), 0, st, L, f.off, f.ticket);
+    // One persistent launch: per tile column the POTRF of the diagonal tile,
+    // the panel TRSM below it and the trailing updates, pipelined on the
+    // 16-column panels, and the columns overlapped through the update
+    // counters (k_factor_all).
+    int64_t ntot = 0;
+    for (int64_t J = 0; J < L.nt; ++J) ntot += 1 + col_tr_blocks(L, J) + col_up_blocks(L, J);
+    if (ntot > 0x7fffffff) return -3;
+    sc.ticket = f.ticket;
+    LAUNCH(STILES_TK_FACTOR, k_factor_all, dim3((unsigned)std::min<int64_t>(ntot, di.cus)), dim3(P3_NT), 0, st, Lm, L,
+           f.Yd, f.cf, f.upd, (const int*)f.off, sc, f.ldp, f.winfo);
     LAUNCH(STILES_TK_OTHER, k_zero_upper, dim3((unsigned)(8 * L.nt)), dim3(NT), 0, st, Lm, L);
     rc = enqueue_corner(Lm, L, f, st);
     if (rc) return rc;
