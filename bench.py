@@ -23,7 +23,7 @@ METRIC = "FP64 factor+selinv GFLOP/s & solves/s, batched vs plain; p50/p99 laten
 PEAK_F64_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
 
 # HBM bytes per launch of the dominant kernel kind, from rocprofv3 FETCH_SIZE /
-# WRITE_SIZE runs scaled by a copy of known size (profiles/k_column_large_hbm_traffic.md),
+# WRITE_SIZE runs scaled by a copy of known size (profiles/k_factor_all_large_hbm_traffic.md),
 # valid only for the kernel sources they were taken with (sha256 prefix of csrc/*)
 # and the workload named.
 MEASURED_TRAFFIC = {("factor", "large"): {"bytes_per_launch": 29.96e6, "sources": "fba78dfea598206f"}}
@@ -59,7 +59,7 @@ def kernel_flops(nb, w, a, b):
         k["update"] += m * m * b
         k["phase1"] += b ** 3 / 3 + m * b * b + b ** 3 / 3
         k["phase2"] += 2 * m * m * b + m * b * b
-        k["factor"] += b ** 3 / 3 + m * b * b + m * m * b   # one k_column launch per tile column
+        k["factor"] += b ** 3 / 3 + m * b * b + m * m * b   # the factor's single launch (k_factor_all)
     k["other"] += a ** 3 / 3          # corner factor
     k["phase1"] += 2 * a ** 3 / 3     # corner TRTRI + LAUUM
     return k
