@@ -26,7 +26,7 @@ PEAK_F64_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
 # WRITE_SIZE runs scaled by a copy of known size (profiles/k_factor_all_large_hbm_traffic.md),
 # valid only for the kernel sources they were taken with (sha256 prefix of csrc/*)
 # and the workload named.
-MEASURED_TRAFFIC = {("factor", "large"): {"bytes_per_launch": 29.96e6, "sources": "fba78dfea598206f"}}
+MEASURED_TRAFFIC = {("factor", "large"): {"bytes_per_launch": 13.248e9, "sources": "b3f45c1e9b4b0cc0"}}
 
 
 def sources_hash() -> str:
@@ -101,6 +101,9 @@ def main() -> int:
     ap.add_argument("--workload", choices=sorted(WORKLOADS), default="large")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="batched: this tile size instead of the autotuner's")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="one device copy of a tile buffer (known bytes) before the timed steps, to scale "
+                         "hardware byte counters")
     ap.add_argument("--jobs", type=int, default=100, help="served: jobs per arrival rate")
     ap.add_argument("--budget-gb", type=float, default=64.0, help="served: HBM budget of the serving loop")
     ap.add_argument("--lanes", type=int, default=3, help="served: concurrent batches")
@@ -149,6 +152,9 @@ def main() -> int:
         _, sinfo = st.selinv(L, lay, out=S, workspace=wss)
         return ld, info, sinfo
 
+    if args.calib_copy:
+        S.copy_(L)                       # 8 * total_doubles bytes read and written
+        torch.cuda.synchronize()
     for i in range(args.warmup):
         ld, info, sinfo = step()
         torch.cuda.synchronize()
