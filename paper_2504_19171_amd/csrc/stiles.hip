@@ -71,8 +71,9 @@ __global__ void k_set_int(int* p, int v) {
 // Pack the canonical band form into the tile layout (every double written).
 // Workgroup g < N (B+1) writes band tile g = J (B+1) + d, i.e. tile (J+d, J);
 // the next N write the arrow tiles J; the last one the corner.  In a band tile
-// thread r writes row r of every column (consecutive threads, consecutive
-// addresses); the tile indices are uniform, so no division per element.
+// thread t writes row t % b of the columns t / b, t / b + 256 / b, ...
+// (consecutive threads, consecutive addresses); the tile indices are uniform,
+// so no division per element.
 __global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, const double* __restrict__ P,
                                             const double* __restrict__ C, double* __restrict__ T, Lay L) {
     const int64_t b = L.b;
@@ -82,9 +83,11 @@ __global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, cons
         const int64_t J = g / (L.bt + 1), d = g % (L.bt + 1);
         double* O = T + g * b * b;
         const bool live = J + d < L.nt;
-        for (int r = threadIdx.x; r < b; r += NT) {
+        const int cstep = (int)(NT / b) > 0 ? (int)(NT / b) : 1;   // b in {64, 128, 192, 256}
+        const int r = (int)(threadIdx.x % b), c0 = (int)(threadIdx.x / b);
+        if (c0 < cstep) {
             const int64_t i = (J + d) * b + r;
-            for (int c = 0; c < b; ++c) {
+            for (int c = c0; c < b; c += cstep) {
                 const int64_t j = J * b + c;
                 double v = 0.0;
                 if (live) {
@@ -1199,53 +1202,47 @@ __global__ __launch_bounds__(NT) void kb_factor_setup(const BInst* bi) {
         *f.winfo = 0x7fffffff;
         *f.err = 0;
     }
-    const int64_t n = I.L.nt * (int64_t)col_stride(I.L) + upd_ints(I.L);   // tile column and update counters
+    const int64_t n = I.L.nt * (int64_t)col_stride(I.L);
     for (int64_t i = threadIdx.x; i < n; i += NT) f.cf[i] = 0;
 }
 
-// The factor of every matrix in one persistent launch, all tasks on one
-// ticket queue, tile column by tile column.  Column J's tickets start at
-// colq[4J] (colq[4 ncol] = all); inside the column, ticket g is local task t
-// of matrix order[g - off[t]] (the matrices with N > J sorted by decreasing
-// task count, so those with more than t tasks come first), i.e. the POTRFs
-// of every matrix first, then every matrix's first TRSM block, and so on.
-// colq[4J + 1], colq[4J + 2], colq[4J + 3]: where off and order of column J
-// sit in `ints`, and T (off has T + 1 entries).  Every matrix's tasks keep the
-// single-matrix order (every wait is for a smaller ticket); across columns
-// they wait on the matrix's update counters as in k_factor_all.
-__global__ __launch_bounds__(P3_NT) void kb_factor_all(const BInst* bi, const int* ints, const int* colq, int ncol,
-                                                    int* ticket, int* err, int64_t spin_limit) {
+// Tile column J of every matrix with N > J in one launch, all its tasks on
+// one ticket queue: ticket g is local task t of matrix order[g - off[t]]
+// (the matrices sorted by decreasing task count, so those with more than t
+// tasks come first), i.e. task 0 (the POTRFs) of every matrix first, then
+// task 1 of every matrix, and so on.  Each matrix's tasks keep their order, so
+// every task waits only for smaller tickets.
+struct BColArgs {
+    const BInst* bi;
+    const int* off;      // [T + 1], off[T] = ntot
+    const int* order;
+    int T;
+    int ntot;
+    int* ticket;
+    int* err;            // the batch's error word
+    int64_t spin_limit;
+};
+__global__ __launch_bounds__(P3_NT) void kb_column(BColArgs a, int64_t J) {
     __shared__ ColSmem sm;
     __shared__ int sh;
     Sched sc;
-    sc.ticket = ticket;
-    sc.err = err;
-    sc.spin_limit = spin_limit;
+    sc.ticket = a.ticket;
+    sc.err = a.err;
+    sc.spin_limit = a.spin_limit;
     sc.withhold = -1;
-    const int ntot = colq[4 * ncol];
     for (;;) {
-        const int g = sched_next(sc, ntot, &sh);
+        const int g = sched_next(sc, a.ntot, &sh);
         if (g < 0) return;
-        int lo = 0, hi = ncol;
+        int lo = 0, hi = a.T;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (colq[4 * mid] <= g) lo = mid; else hi = mid;
-        }
-        const int64_t J = lo;
-        const int rel = g - colq[4 * lo];
-        const int* off = ints + colq[4 * lo + 1];
-        const int* order = ints + colq[4 * lo + 2];
-        lo = 0;
-        hi = colq[4 * J + 3];
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (off[mid] <= rel) lo = mid; else hi = mid;
+            if (a.off[mid] <= g) lo = mid; else hi = mid;
         }
         const int t = lo;
-        const BInst& I = bi[order[rel - off[t]]];
+        const BInst& I = a.bi[a.order[g - a.off[t]]];
         const FactorWs f = factor_ws(I.L, I.ws);
         if (!col_task(sm, sh, I.Lm, I.L, J, f.Yd + J * (int64_t)I.L.b * 16, f.cf + J * col_stride(I.L), sc,
-                      f.ldp + 2 * J, f.winfo, t, f.upd))
+                      f.ldp + 2 * J, f.winfo, t, nullptr))
             return;
     }
 }
@@ -1708,8 +1705,7 @@ static int batch_plan(const stiles_batch_item* items, int count, bool need_sigma
         tmax = std::max<int64_t>(tmax, 1 + col_tr_blocks(L, 0) + col_up_blocks(L, 0));
     }
     const size_t nseg = 6 * ((size_t)count + 1);
-    const size_t nint = (size_t)count + 1 + (size_t)pl.maxN + (size_t)pl.maxN * (size_t)(tmax + 1) + (size_t)sumN +
-                        4 * ((size_t)pl.maxN + 1);
+    const size_t nint = (size_t)count + 1 + (size_t)pl.maxN + (size_t)pl.maxN * (size_t)(tmax + 1) + (size_t)sumN;
     pl.table = align256(sizeof(BInst) * (size_t)count) + align256(sizeof(BSeg) * nseg) + align256(sizeof(int) * nint);
     size_t o = pl.table;
     for (int k = 0; k < count; ++k) {
@@ -2125,21 +2121,6 @@ int stiles_factor_batched(const stiles_batch_item* items, int32_t count, void* w
         q.order_at = ints.size();
         for (const auto& e : nt_k) ints.push_back(e.second);
     }
-    // column table of the single launch: start ticket, off, order, T
-    const size_t colq_at = ints.size();
-    int64_t start = 0;
-    for (int64_t J = 0; J < pl.maxN; ++J) {
-        ints.push_back((int)start);
-        ints.push_back((int)cq[J].off_at);
-        ints.push_back((int)cq[J].order_at);
-        ints.push_back(cq[J].T);
-        start += cq[J].ntot;
-    }
-    if (start > 0x7fffffff) return -1;
-    ints.push_back((int)start);
-    ints.push_back(0);
-    ints.push_back(0);
-    ints.push_back(0);
     int rc = batch_upload(bi, segs, ints, ws, st);
     if (rc) return rc;
     const BInst* dbi = (const BInst*)ws;
@@ -2154,8 +2135,11 @@ int stiles_factor_batched(const stiles_batch_item* items, int32_t count, void* w
         tm_end(tm, STILES_TK_OTHER, st);
     }
     LAUNCH(STILES_TK_OTHER, kb_factor_setup, dim3(count), dim3(NT), 0, st, dbi);
-    LAUNCH(STILES_TK_FACTOR, kb_factor_all, dim3((unsigned)std::min<int64_t>(start, di.cus)), dim3(P3_NT), 0, st, dbi,
-           (const int*)dint, (const int*)(dint + colq_at), (int)pl.maxN, dint + tick_at, dint + err_at, spin);
+    for (int64_t J = 0; J < pl.maxN; ++J) {
+        const ColQ& q = cq[J];
+        const BColArgs a{dbi, dint + q.off_at, dint + q.order_at, q.T, q.ntot, dint + tick_at + J, dint + err_at, spin};
+        LAUNCH(STILES_TK_FACTOR, kb_column, dim3((unsigned)std::min(q.ntot, di.cus)), dim3(P3_NT), 0, st, a, J);
+    }
     {
         const BArgs a{dbi, dseg + zu_at, zu_n, spin};
         LAUNCH(STILES_TK_OTHER, kb_zero_upper, dim3((unsigned)zu_grid), dim3(NT), 0, st, a);
