@@ -799,25 +799,38 @@ __global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, La
 // Phase 2 as one persistent kernel
 // ---------------------------------------------------------------------------
 // Tile column J needs the off-diagonal tiles S(J) x S(J) of Sigma, where
-// S(J) = band tiles J+1..J+s and the arrow.  Everything in S(J) x S(J) except
-// what involves tile J+1 is final once column J+2 is done, so each output is
-// split into an "early" part (k over the far tiles J+2..J+s and the arrow),
-// which can start two columns ahead, and a "late" part (k = J+1).  Every task
-// is a 32 x 32 block whose reduction is spread over the 4 wavefronts of a
-// workgroup, so that the tasks on the dependency chain stay short:
-//   E  : Sigma_{i,J}  = -sum_{k far} Sigma_{i,k} Lhat_{k,J}     i far
-//   E1 : Sigma_{J+1,J} = -sum_{k far} Sigma_{J+1,k} Lhat_{k,J}
-//   L  : Sigma_{i,J} -= Sigma_{i,J+1} Lhat_{J+1,J}               i far
+// S(J) = band tiles J+1..J+s and the arrow.  Each output block is summed over
+// k in three parts, by how late its operands become final:
+//   k over the far tiles J+3..J+s and the arrow: final once the off-diagonal
+//     tiles of column J+2 are (two and a half columns ahead);
+//   k = J+2: final once column J+2 is done;
+//   k = J+1: final once column J+1's off-diagonal tiles (rows i far) or its
+//     diagonal tile (row J+1) are.
+// Every task is a 32 x 32 block whose reduction is spread over the 4
+// wavefronts of a workgroup, so that the tasks on the dependency chain stay
+// short ("far rows" = tiles J+2..J+s and the arrow):
+//   EA : Sigma_{i,J}   = -sum_{k = J+3.., arrow} Sigma_{i,k} Lhat_{k,J}   i far
+//   EB : Sigma_{i,J}  -= Sigma_{i,J+2} Lhat_{J+2,J}                      i far
+//   L  : Sigma_{i,J}  -= Sigma_{i,J+1} Lhat_{J+1,J}                      i far
+//   E1A: Sigma_{J+1,J} = -sum_{k = J+3.., arrow} Sigma_{J+1,k} Lhat_{k,J}
+//   E1B: Sigma_{J+1,J} -= Sigma_{J+1,J+2} Lhat_{J+2,J}
 //   L1 : Sigma_{J+1,J} -= Sigma_{J+1,J+1} Lhat_{J+1,J}
 //   DA : Sigma_JJ = X_J^T X_J - sum_{i far} Lhat_{i,J}^T Sigma_{i,J}       (lower blocks)
 //   DB : Sigma_JJ -= Lhat_{J+1,J}^T Sigma_{J+1,J}, then mirrored           (lower blocks)
-// Dependencies (counters per tile column, "done(J)" = its last group):
-//   E(J): done(J+2);  E1(J), L(J): off-diagonals of J+1 final (and E(J));
-//   L1(J): Sigma_{J+1,J+1} final and E1(J);  DA(J): L(J);  DB(J): DA(J), L1(J).
-// Ticket order: groups J = N-1 .. 0, group J = [E(J-1), E1(J), L(J), L1(J),
-// DA(J), DB(J)] (group N-1 also starts with E(N-1)); every task depends only
-// on tasks of earlier groups or earlier in its own group.
-enum { P2_E = 0, P2_E1, P2_L, P2_L1, P2_DA, P2_DB, P2_KINDS };
+// Dependencies (counters per kind and tile column; "offdiag(J)": L(J), L1(J)
+// done, or EA(J) for the last column; "far(J)": L(J) done, or EA(J) for the
+// last column; "done(J)": DB(J), or DA(J) for the last column):
+//   EA(J): offdiag(J+2);          EB(J): done(J+2), EA(J);
+//   E1A(J): far(J+1);             E1B(J): L1(J+1), E1A(J);
+//   L(J): offdiag(J+1), EB(J) (EA(J) when s < 2);
+//   L1(J): done(J+1), E1B(J) (E1A(J) when s < 2);
+//   DA(J): far(J);                DB(J): DA(J), L1(J).
+// Ticket order: groups G = N-1 .. 0, group G = [EA(G-1), E1B(G), L(G),
+// E1A(G-1), EB(G-1), L1(G), DA(G), DB(G)] (group N-1 also starts with
+// EA(N-1)); every task depends only on tasks of earlier groups or earlier in
+// its own group.  The order puts each task's ticket close to the time it
+// becomes ready, so few workgroups sit on a ticket that is still waiting.
+enum { P2_EA = 0, P2_EB, P2_E1A, P2_E1B, P2_L, P2_L1, P2_DA, P2_DB, P2_KINDS };
 
 struct P2 {
     double* S;
@@ -832,15 +845,18 @@ struct P2Counts {
     int n[P2_KINDS];
 };
 
-// Task counts of tile column J.
+// Task counts of tile column J.  EA and E1A exist (possibly with an empty
+// reduction, writing zeros) wherever their rows do.
 __host__ __device__ inline P2Counts p2_counts(const Lay& L, int64_t J) {
     P2Counts c;
     const int s = L.s(J);
     const int C32 = L.b / 32;
     const int far = s > 1 ? s - 1 : 0;
     const int nf32 = far * C32 + (L.ap + 31) / 32;
-    c.n[P2_E] = nf32 * C32;
-    c.n[P2_E1] = s >= 1 ? C32 * C32 : 0;
+    c.n[P2_EA] = nf32 * C32;
+    c.n[P2_EB] = s >= 2 ? nf32 * C32 : 0;
+    c.n[P2_E1A] = s >= 1 ? C32 * C32 : 0;
+    c.n[P2_E1B] = s >= 2 ? C32 * C32 : 0;
     c.n[P2_L] = s >= 1 ? nf32 * C32 : 0;
     c.n[P2_L1] = s >= 1 ? C32 * C32 : 0;
     c.n[P2_DA] = C32 * (C32 + 1) / 2;
@@ -848,13 +864,24 @@ __host__ __device__ inline P2Counts p2_counts(const Lay& L, int64_t J) {
     return c;
 }
 
-// Tasks in group J (see the ticket order above).
-__host__ __device__ inline int p2_group_tasks(const Lay& L, int64_t J) {
-    const P2Counts c = p2_counts(L, J);
-    int t = c.n[P2_E1] + c.n[P2_L] + c.n[P2_L1] + c.n[P2_DA] + c.n[P2_DB];
-    if (J >= 1) t += p2_counts(L, J - 1).n[P2_E];
-    if (J == L.nt - 1) t += c.n[P2_E];
-    return t;
+// Slot i of group G: the kind and the tile column offset (0 or -1) of its tasks.
+#define P2_SLOTS 8
+__host__ __device__ inline void p2_slot(int i, int& kind, int& dj) {
+    const int k[P2_SLOTS] = {P2_EA, P2_E1B, P2_L, P2_E1A, P2_EB, P2_L1, P2_DA, P2_DB};
+    const int d[P2_SLOTS] = {-1, 0, 0, -1, -1, 0, 0, 0};
+    kind = k[i];
+    dj = d[i];
+}
+
+// Tasks in group G (see the ticket order above).
+__host__ __device__ inline int p2_group_tasks(const Lay& L, int64_t G) {
+    const P2Counts c = p2_counts(L, G);
+    int t = (G == L.nt - 1) ? c.n[P2_EA] : 0;
+    if (G >= 1) {
+        const P2Counts c1 = p2_counts(L, G - 1);
+        t += c1.n[P2_EA] + c1.n[P2_E1A] + c1.n[P2_EB];
+    }
+    return t + c.n[P2_E1B] + c.n[P2_L] + c.n[P2_L1] + c.n[P2_DA] + c.n[P2_DB];
 }
 
 __device__ inline void p2_setup_body(const P2& p, int* ticket, int* err) {
@@ -900,22 +927,25 @@ __device__ inline void p2_far_row(const Lay& L, int s, int rbg, int rb, int& d, 
     else { d = ARW; rbl = rbg - far * per; }
 }
 
-// Is "done(J)" reached (all of column J final)?  Waits on the counters.
-__device__ inline bool p2_wait_done(const P2& p, const Sched& sc, int64_t J, int* sh) {
-    const P2Counts c = p2_counts(p.L, J);
-    const int64_t N = p.L.nt;
-    if (c.n[P2_DB] > 0) return sched_wait(sc, &p.cnt[P2_DB * N + J], c.n[P2_DB], sh);
-    return sched_wait(sc, &p.cnt[P2_DA * N + J], c.n[P2_DA], sh);
+// Wait until every task of the given kind and tile column has finished.
+__device__ inline bool p2_wait_all(const P2& p, const Sched& sc, int kind, int64_t J, int* sh) {
+    return sched_wait(sc, &p.cnt[kind * p.L.nt + J], p2_counts(p.L, J).n[kind], sh);
 }
-
-// Are the off-diagonal tiles of column J final?
+// done(J): all of column J final.
+__device__ inline bool p2_wait_done(const P2& p, const Sched& sc, int64_t J, int* sh) {
+    if (J >= p.L.nt) return true;
+    return p2_wait_all(p, sc, p.L.s(J) >= 1 ? P2_DB : P2_DA, J, sh);
+}
+// far(J): the far rows of column J final.
+__device__ inline bool p2_wait_far(const P2& p, const Sched& sc, int64_t J, int* sh) {
+    if (J >= p.L.nt) return true;
+    return p2_wait_all(p, sc, p.L.s(J) >= 1 ? P2_L : P2_EA, J, sh);
+}
+// offdiag(J): every off-diagonal tile of column J final.
 __device__ inline bool p2_wait_offdiag(const P2& p, const Sched& sc, int64_t J, int* sh) {
-    const P2Counts c = p2_counts(p.L, J);
-    const int64_t N = p.L.nt;
-    if (c.n[P2_L1] > 0)
-        return sched_wait(sc, &p.cnt[P2_L * N + J], c.n[P2_L], sh) &&
-               sched_wait(sc, &p.cnt[P2_L1 * N + J], c.n[P2_L1], sh);
-    return sched_wait(sc, &p.cnt[P2_E * N + J], c.n[P2_E], sh);
+    if (J >= p.L.nt) return true;
+    if (p.L.s(J) >= 1) return p2_wait_all(p, sc, P2_L, J, sh) && p2_wait_all(p, sc, P2_L1, J, sh);
+    return p2_wait_all(p, sc, P2_EA, J, sh);
 }
 
 #define P2_SMEM_DOUBLES (WS_SMEM_DOUBLES + 32 * WR_LD)
@@ -929,22 +959,28 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
     const int C32 = L.b / 32;
     const int s = L.s(J);
     const int far = s > 1 ? s - 1 : 0;
-    // output block and the reduction: L, L1, DB run over tile J+1 only (one
-    // segment of b); DA over the far tiles and the arrow
-    int d = 0, rbl = 0, rb = 0, cb = 0, nseg, ktot;
-    const bool rowtask = kind <= P2_L1;            // E, E1, L, L1
-    const bool kfar = kind == P2_E || kind == P2_E1;  // reduction over the far tiles
+    // the reduction: band tiles J+e0 .. J+e0+nband-1, then the arrow if karw
+    int e0, nband;
+    bool karw;
+    switch (kind) {
+        case P2_EA: case P2_E1A: e0 = 3; nband = s > 2 ? s - 2 : 0; karw = L.ap > 0; break;
+        case P2_EB: case P2_E1B: e0 = 2; nband = 1; karw = false; break;
+        case P2_DA: e0 = 2; nband = far; karw = L.ap > 0; break;
+        default: e0 = 1; nband = 1; karw = false;   // L, L1, DB
+    }
+    const int nseg = nband + (karw ? 1 : 0);
+    const int ktot = nband * L.b + (karw ? L.ap : 0);
+    // the output block
+    int d = 0, rbl = 0, rb = 0, cb = 0;
+    const bool rowtask = kind < P2_DA;
     if (rowtask) {
-        if (kind == P2_E || kind == P2_L) p2_far_row(L, s, u / C32, 32, d, rbl);
+        if (kind == P2_EA || kind == P2_EB || kind == P2_L) p2_far_row(L, s, u / C32, 32, d, rbl);
         else { d = 1; rbl = u / C32; }
         cb = u % C32;
-        nseg = kfar ? far + (L.ap > 0 ? 1 : 0) : 1;
-        ktot = kfar ? far * L.b + L.ap : L.b;
     } else {
         tri_decode(u, rb, cb);
-        nseg = (kind == P2_DA) ? far + (L.ap > 0 ? 1 : 0) : 1;
-        ktot = (kind == P2_DA) ? far * L.b + L.ap : L.b;
     }
+    const bool zero_base = kind == P2_EA || kind == P2_E1A;
     double* O;
     int64_t ldo;
     int mv = 32;
@@ -956,13 +992,13 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
         ldo = L.b;
     }
     const bool diag = (kind >= P2_DA) && rb == cb;
-    // the partial already stored (L, L1, DB) is final once the task runs:
-    // read it now so its round trip overlaps the products
+    // the partial already stored (EB, E1B, L, L1, DB) is final once the task
+    // runs: read it now so its round trip overlaps the products
     double ov[4];
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int e = threadIdx.x + 256 * q, i = e & 31, j = e >> 5;
-        ov[q] = (kfar || i >= mv || (diag && i < j)) ? 0.0 : ld_coh(O + i + (int64_t)j * ldo);
+        ov[q] = (zero_base || i >= mv || (diag && i < j)) ? 0.0 : ld_coh(O + i + (int64_t)j * ldo);
     }
     dbl4 acc[2][2];
 #pragma unroll
@@ -970,15 +1006,14 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
     wave_segs(acc, nseg, ktot, smem, [&](int q) {
+        const int e = (q < nband) ? e0 + q : ARW;
         if (rowtask) {
-            const int e = kfar ? ((q < far) ? q + 2 : ARW) : 1;
             const double* a; int64_t lda; int ta, av;
             p2_sigma_rows(L, p.S, J, d, rbl, 32, e, a, lda, ta, av);
             if (e != ARW)
                 return mkseg(a, lda, ta, p.W + L.band(J, e) + (int64_t)cb * 32 * L.b, L.b, 0, L.b, av, 1, 0);
             return mkseg(a, lda, ta, p.W + L.arrow(J) + (int64_t)cb * 32 * L.ap, L.ap, 0, L.ap, av, 1, 0);
         }
-        const int e = (kind == P2_DB) ? 1 : ((q < far) ? q + 2 : ARW);
         if (e != ARW)
             return mkseg(p.W + L.band(J, e) + (int64_t)rb * 32 * L.b, L.b, 1,
                          p.S + L.band(J, e) + (int64_t)cb * 32 * L.b, L.b, 0, L.b, 32, 0, 1);
@@ -988,8 +1023,8 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
     TRACE(t, 4, wall_clock64());
     wave_reduce(acc, smem, red);
     TRACE(t, 5, wall_clock64());
-    // out = base - red, base = the partial already stored (L, L1, DB),
-    // Sigma_JJ's initial value X^T X (DA), or 0 (E, E1)
+    // out = base - red, base = the partial already stored (EB, E1B, L, L1,
+    // DB), Sigma_JJ's initial value X^T X (DA), or 0 (EA, E1A)
     const bool mirror = (kind == P2_DB) || (kind == P2_DA && mirror_da);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -1030,48 +1065,44 @@ __device__ inline void p2_run(const P2& p, const Sched& sc, double* smem, int* s
         // decode (kind, J, index) inside group G
         int kind = -1;
         int64_t J = G;
-        {
-            const P2Counts cg = p2_counts(L, G);
-            if (G == N - 1) {
-                if (u < cg.n[P2_E]) kind = P2_E;
-                else u -= cg.n[P2_E];
-            }
-            if (kind < 0 && G >= 1) {
-                const int ne = p2_counts(L, G - 1).n[P2_E];
-                if (u < ne) { kind = P2_E; J = G - 1; }
-                else u -= ne;
-            }
-            for (int k = P2_E1; kind < 0 && k < P2_KINDS; ++k) {
-                if (u < cg.n[k]) kind = k;
-                else u -= cg.n[k];
-            }
+        if (G == N - 1) {
+            const int n = p2_counts(L, G).n[P2_EA];
+            if (u < n) kind = P2_EA;
+            else u -= n;
         }
-        const P2Counts c = p2_counts(L, J);
+        for (int i = 0; kind < 0 && i < P2_SLOTS; ++i) {
+            int k, dj;
+            p2_slot(i, k, dj);
+            if (G + dj < 0) continue;
+            const int n = p2_counts(L, G + dj).n[k];
+            if (u < n) { kind = k; J = G + dj; }
+            else u -= n;
+        }
         int* my = &p.cnt[kind * N + J];
 
         // dependencies
         bool ok = true;
+        const bool two = L.s(J) >= 2;
         switch (kind) {
-            case P2_E: if (J + 2 < N) ok = p2_wait_done(p, sc, J + 2, &sh[1]); break;
-            case P2_E1: ok = p2_wait_offdiag(p, sc, J + 1, &sh[1]); break;
+            case P2_EA: ok = p2_wait_offdiag(p, sc, J + 2, &sh[1]); break;
+            case P2_EB: ok = p2_wait_done(p, sc, J + 2, &sh[1]) && p2_wait_all(p, sc, P2_EA, J, &sh[1]); break;
+            case P2_E1A: ok = p2_wait_far(p, sc, J + 1, &sh[1]); break;
+            case P2_E1B:
+                ok = p2_wait_all(p, sc, P2_L1, J + 1, &sh[1]) && p2_wait_all(p, sc, P2_E1A, J, &sh[1]);
+                break;
             case P2_L:
-                ok = p2_wait_offdiag(p, sc, J + 1, &sh[1]) && sched_wait(sc, &p.cnt[P2_E * N + J], c.n[P2_E], &sh[1]);
+                ok = p2_wait_offdiag(p, sc, J + 1, &sh[1]) && p2_wait_all(p, sc, two ? P2_EB : P2_EA, J, &sh[1]);
                 break;
             case P2_L1:
-                ok = p2_wait_done(p, sc, J + 1, &sh[1]) && sched_wait(sc, &p.cnt[P2_E1 * N + J], c.n[P2_E1], &sh[1]);
+                ok = p2_wait_done(p, sc, J + 1, &sh[1]) && p2_wait_all(p, sc, two ? P2_E1B : P2_E1A, J, &sh[1]);
                 break;
-            case P2_DA:
-                ok = (c.n[P2_L] > 0) ? sched_wait(sc, &p.cnt[P2_L * N + J], c.n[P2_L], &sh[1])
-                                     : sched_wait(sc, &p.cnt[P2_E * N + J], c.n[P2_E], &sh[1]);
-                break;
-            default:
-                ok = sched_wait(sc, &p.cnt[P2_DA * N + J], c.n[P2_DA], &sh[1]) &&
-                     sched_wait(sc, &p.cnt[P2_L1 * N + J], c.n[P2_L1], &sh[1]);
+            case P2_DA: ok = p2_wait_far(p, sc, J, &sh[1]); break;
+            default: ok = p2_wait_all(p, sc, P2_DA, J, &sh[1]) && p2_wait_all(p, sc, P2_L1, J, &sh[1]);
         }
         if (!ok) break;
         TRACE(t, 1, wall_clock64());
 
-        p2_task_small(p, kind, J, u, c.n[P2_DB] == 0, smem, red, t);
+        p2_task_small(p, kind, J, u, L.s(J) == 0, smem, red, t);
         sched_signal(sc, my, t);
         TRACE(t, 2, wall_clock64());
         TRACE(t, 3, (unsigned long long)kind | ((unsigned long long)J << 8) | ((unsigned long long)blockIdx.x << 40));
