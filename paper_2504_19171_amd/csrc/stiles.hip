@@ -70,50 +70,92 @@ __global__ void k_set_int(int* p, int v) {
 
 // Pack the canonical band form into the tile layout (every double written).
 // Workgroup g < N (B+1) writes band tile g = J (B+1) + d, i.e. tile (J+d, J);
-// the next N write the arrow tiles J; the last one the corner.  In a band tile
-// thread t writes row t % b of the columns t / b, t / b + 256 / b, ...
-// (consecutive threads, consecutive addresses); the tile indices are uniform,
-// so no division per element.
+// the next N write the arrow tiles J; the last one the corner.
+//
+// A band tile is written 32 columns at a time through LDS.  Column c of tile
+// (J+d, J) holds A[(J+d) b + r, J b + c]; in the band form that is
+// ab[d b + r - c, J b + c] (on and below the diagonal) and ab[c - r, J b + r]
+// (above it, diagonal tiles only).  For a fixed band-form row k both are 32
+// consecutive doubles over the 32 columns, so the reads run along the rows of
+// ab, the block is assembled in LDS and written out column by column: both
+// sides coalesced.  The arrow tiles go the same way: a row of P is contiguous,
+// a tile column is contiguous.
+#define PACK_CB 32
+#define PACK_RB 256
+#define PACK_SMEM_DOUBLES (PACK_CB * (PACK_RB + 1))
 __global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, const double* __restrict__ P,
                                             const double* __restrict__ C, double* __restrict__ T, Lay L) {
-    const int64_t b = L.b;
+    __shared__ double blk[PACK_SMEM_DOUBLES];   // [c][r]: column c at c * b (band) or c * (rows + 1) (arrow)
+    const int b = L.b;
     const int64_t nband = L.nt * (int64_t)(L.bt + 1);
     const int64_t g = blockIdx.x;
+    const int tid = threadIdx.x;
     if (g < nband) {
-        const int64_t J = g / (L.bt + 1), d = g % (L.bt + 1);
-        double* O = T + g * b * b;
+        const int64_t J = g / (L.bt + 1);
+        const int d = (int)(g % (L.bt + 1));
+        double* O = T + g * (int64_t)b * b;
         const bool live = J + d < L.nt;
-        const int cstep = (int)(NT / b) > 0 ? (int)(NT / b) : 1;   // b in {64, 128, 192, 256}
-        const int r = (int)(threadIdx.x % b), c0 = (int)(threadIdx.x / b);
-        if (c0 < cstep) {
-            const int64_t i = (J + d) * b + r;
-            for (int c = c0; c < b; c += cstep) {
-                const int64_t j = J * b + c;
-                double v = 0.0;
-                if (live) {
-                    if (i < L.nb && j < L.nb) {
-                        const int64_t k = i >= j ? i - j : j - i, lo = i >= j ? j : i;
-                        if (k <= L.w) v = ab[k * L.nb + lo];
-                    } else if (i == j) {
-                        v = 1.0;
+        const int64_t i0 = (J + d) * b, j0 = J * b;   // global row / column of the tile's (0, 0)
+        for (int cb = 0; cb < b; cb += PACK_CB) {
+            // defaults: 0, or 1 on the diagonal past the band part (identity padding)
+            for (int e = tid; e < PACK_CB * b; e += NT) {
+                const int c = e / b, r = e % b;
+                blk[e] = (live && d == 0 && r == cb + c && i0 + r >= L.nb) ? 1.0 : 0.0;
+            }
+            __syncthreads();
+            if (live) {
+                // on and below the diagonal: k = d b + r - c', c' = cb + c
+                const int klo = imax_(0, d * b - cb - (PACK_CB - 1)), khi = imin_((int)L.w, d * b + b - 1 - cb);
+                const int n = (khi - klo + 1) * PACK_CB;
+#pragma unroll 4
+                for (int e = tid; e < n; e += NT) {
+                    const int k = klo + e / PACK_CB, c = e % PACK_CB;
+                    const int r = k - d * b + cb + c;
+                    const int64_t j = j0 + cb + c;
+                    if (r >= 0 && r < b && i0 + r < L.nb && j < L.nb) blk[c * b + r] = ab[(int64_t)k * L.nb + j];
+                }
+                if (d == 0) {
+                    // above the diagonal: k = c' - r >= 1, value ab[k, j0 + r]
+                    const int khi2 = imin_((int)L.w, cb + PACK_CB - 1);
+                    const int n2 = imax_(khi2, 0) * PACK_CB;
+#pragma unroll 4
+                    for (int e = tid; e < n2; e += NT) {
+                        const int k = 1 + e / PACK_CB, c = e % PACK_CB;
+                        const int r = cb + c - k;
+                        if (r >= 0 && j0 + cb + c < L.nb) blk[c * b + r] = ab[(int64_t)k * L.nb + j0 + r];
                     }
                 }
-                O[r + c * b] = v;
             }
+            __syncthreads();
+            for (int e = tid; e < PACK_CB * b; e += NT) O[(int64_t)cb * b + e] = blk[e];
+            __syncthreads();
         }
     } else if (g < nband + L.nt) {
         const int64_t J = g - nband;
         double* O = T + L.arrow(J);
         const int ap = L.ap;
-        for (int e = threadIdx.x; e < ap * (int)b; e += NT) {
-            const int r = e % ap, c = e / ap;
-            const int64_t j = J * b + c;
-            O[e] = (r < L.a && j < L.nb) ? P[r * L.nb + j] : 0.0;
+        const int64_t j0 = J * b;
+        for (int cb = 0; cb < b; cb += PACK_CB) {
+            for (int rb = 0; rb < ap; rb += PACK_RB) {
+                const int nr = imin_(PACK_RB, ap - rb);
+                // rows r of P over the block's 32 columns (contiguous), into [c][r]
+                for (int e = tid; e < nr * PACK_CB; e += NT) {
+                    const int r = e / PACK_CB, c = e % PACK_CB;
+                    const int64_t j = j0 + cb + c;
+                    blk[c * (nr + 1) + r] = (rb + r < L.a && j < L.nb) ? P[(int64_t)(rb + r) * L.nb + j] : 0.0;
+                }
+                __syncthreads();
+                for (int e = tid; e < nr * PACK_CB; e += NT) {
+                    const int c = e / nr, r = e % nr;
+                    O[(int64_t)(cb + c) * ap + rb + r] = blk[c * (nr + 1) + r];
+                }
+                __syncthreads();
+            }
         }
     } else {
         double* O = T + L.corner();
         const int ap = L.ap;
-        for (int e = threadIdx.x; e < ap * ap; e += NT) {
+        for (int e = tid; e < ap * ap; e += NT) {
             const int r = e % ap, c = e / ap;
             O[e] = (r < L.a && c < L.a) ? C[r * L.a + c] : (r == c ? 1.0 : 0.0);
         }
@@ -825,11 +867,12 @@ __global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, La
 //   L(J): offdiag(J+1), EB(J) (EA(J) when s < 2);
 //   L1(J): done(J+1), E1B(J) (E1A(J) when s < 2);
 //   DA(J): far(J);                DB(J): DA(J), L1(J).
-// Ticket order: groups G = N-1 .. 0, group G = [EA(G-1), E1B(G), L(G),
-// E1A(G-1), EB(G-1), L1(G), DA(G), DB(G)] (group N-1 also starts with
+// Ticket order: groups G = N-1 .. 0, group G = [EA(G-1), L(G), E1B(G),
+// EB(G-1), E1A(G-1), L1(G), DA(G), DB(G)] (group N-1 also starts with
 // EA(N-1)); every task depends only on tasks of earlier groups or earlier in
 // its own group.  The order puts each task's ticket close to the time it
-// becomes ready, so few workgroups sit on a ticket that is still waiting.
+// becomes ready, so few workgroups sit on a ticket that is still waiting (it
+// was the fastest of the orders timed).
 enum { P2_EA = 0, P2_EB, P2_E1A, P2_E1B, P2_L, P2_L1, P2_DA, P2_DB, P2_KINDS };
 
 struct P2 {
@@ -867,7 +910,7 @@ __host__ __device__ inline P2Counts p2_counts(const Lay& L, int64_t J) {
 // Slot i of group G: the kind and the tile column offset (0 or -1) of its tasks.
 #define P2_SLOTS 8
 __host__ __device__ inline void p2_slot(int i, int& kind, int& dj) {
-    const int k[P2_SLOTS] = {P2_EA, P2_E1B, P2_L, P2_E1A, P2_EB, P2_L1, P2_DA, P2_DB};
+    const int k[P2_SLOTS] = {P2_EA, P2_L, P2_E1B, P2_EB, P2_E1A, P2_L1, P2_DA, P2_DB};
     const int d[P2_SLOTS] = {-1, 0, 0, -1, -1, 0, 0, 0};
     kind = k[i];
     dj = d[i];
