@@ -868,7 +868,7 @@ __global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, La
 //   L1(J): done(J+1), E1B(J) (E1A(J) when s < 2);
 //   DA(J): far(J);                DB(J): DA(J), L1(J).
 // Ticket order: groups G = N-1 .. 0, group G = [EA(G-1), L(G), E1B(G),
-// EB(G-1), E1A(G-1), L1(G), DA(G), DB(G)] (group N-1 also starts with
+// E1A(G-1), EB(G-1), L1(G), DA(G), DB(G)] (group N-1 also starts with
 // EA(N-1)); every task depends only on tasks of earlier groups or earlier in
 // its own group.  The order puts each task's ticket close to the time it
 // becomes ready, so few workgroups sit on a ticket that is still waiting (it
@@ -910,7 +910,7 @@ __host__ __device__ inline P2Counts p2_counts(const Lay& L, int64_t J) {
 // Slot i of group G: the kind and the tile column offset (0 or -1) of its tasks.
 #define P2_SLOTS 8
 __host__ __device__ inline void p2_slot(int i, int& kind, int& dj) {
-    const int k[P2_SLOTS] = {P2_EA, P2_L, P2_E1B, P2_EB, P2_E1A, P2_L1, P2_DA, P2_DB};
+    const int k[P2_SLOTS] = {P2_EA, P2_L, P2_E1B, P2_E1A, P2_EB, P2_L1, P2_DA, P2_DB};
     const int d[P2_SLOTS] = {-1, 0, 0, -1, -1, 0, 0, 0};
     kind = k[i];
     dj = d[i];
