@@ -96,6 +96,27 @@ __global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, cons
         double* O = T + g * (int64_t)b * b;
         const bool live = J + d < L.nt;
         const int64_t i0 = (J + d) * b, j0 = J * b;   // global row / column of the tile's (0, 0)
+        if (b == 64) {
+            // 64 x 64 tiles: the staging costs more than it saves (each block
+            // would read 95 band-form rows for 64 tile rows); thread t writes
+            // row t % 64 of columns t / 64, t / 64 + 4, ...
+            const int r = tid % 64;
+            const int64_t i = i0 + r;
+            for (int c = tid / 64; c < 64; c += NT / 64) {
+                const int64_t j = j0 + c;
+                double v = 0.0;
+                if (live) {
+                    if (i < L.nb && j < L.nb) {
+                        const int64_t k = i >= j ? i - j : j - i, lo = i >= j ? j : i;
+                        if (k <= L.w) v = ab[k * L.nb + lo];
+                    } else if (i == j) {
+                        v = 1.0;
+                    }
+                }
+                O[r + c * 64] = v;
+            }
+            return;
+        }
         for (int cb = 0; cb < b; cb += PACK_CB) {
             // defaults: 0, or 1 on the diagonal past the band part (identity padding)
             for (int e = tid; e < PACK_CB * b; e += NT) {
@@ -676,15 +697,18 @@ __global__ __launch_bounds__(P3_NT) void k_factor_all(double* Lm, Lay L, double*
 }
 
 // First ticket of every tile column (off[N] = all tickets), and the ticket counter.
+// A column's task count depends on J only through s(J): every column before
+// J1 = N - B has the full count, so off[J] is J1 (or J) times that count plus
+// at most B tail terms, one thread per entry.
 __global__ void k_factor_offsets(Lay L, int* off, int* ticket) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int acc = 0;
-    for (int64_t J = 0; J < L.nt; ++J) {
-        off[J] = acc;
-        acc += 1 + col_tr_blocks(L, J) + col_up_blocks(L, J);
+    const int64_t N = L.nt, J1 = imax64(0, N - L.bt);
+    const int64_t cs = J1 > 0 ? 1 + col_tr_blocks(L, 0) + col_up_blocks(L, 0) : 0;
+    for (int64_t J = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; J <= N; J += (int64_t)gridDim.x * blockDim.x) {
+        int64_t acc = (J < J1 ? J : J1) * cs;
+        for (int64_t K = J1; K < J; ++K) acc += 1 + col_tr_blocks(L, K) + col_up_blocks(L, K);
+        off[J] = (int)acc;
     }
-    off[L.nt] = acc;
-    *ticket = 0;
+    if (blockIdx.x == 0 && threadIdx.x == 0) *ticket = 0;
 }
 
 // C (rows x rows, lower blocks) -= P P^T, P rows x K (generic, corner blocking).
@@ -1928,7 +1952,7 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     LAUNCH(STILES_TK_OTHER, k_set_int, dim3(1), dim3(64), 0, st, f.err, 0);
     LAUNCH(STILES_TK_OTHER, k_zero_ints, dim3(grid_for(L.nt * (int64_t)cstride + upd_ints(L))), dim3(NT), 0, st,
            f.cf, L.nt * (int64_t)cstride + upd_ints(L));
-    LAUNCH(STILES_TK_OTHER, k_factor_offsets, dim3(1), dim3(64), 0, st, L, f.off, f.ticket);
+    LAUNCH(STILES_TK_OTHER, k_factor_offsets, dim3((unsigned)((L.nt + NT) / NT)), dim3(NT), 0, st, L, f.off, f.ticket);
     // One persistent launch: per tile column the POTRF of the diagonal tile,
     // the panel TRSM below it and the trailing updates, pipelined on the
     // 16-column panels, and the columns overlapped through the update
