@@ -26,7 +26,7 @@ PEAK_F64_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
 # WRITE_SIZE runs scaled by a copy of known size (profiles/k_factor_all_large_hbm_traffic.md),
 # valid only for the kernel sources they were taken with (sha256 prefix of csrc/*)
 # and the workload named.
-MEASURED_TRAFFIC = {("factor", "large"): {"bytes_per_launch": 13.265e9, "sources": "2e2039b0434e1363"}}
+MEASURED_TRAFFIC = {("factor", "large"): {"bytes_per_launch": 13.240e9, "sources": "db321231634b1f5e"}}
 
 
 def sources_hash() -> str:
