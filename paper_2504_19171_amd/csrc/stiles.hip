@@ -1972,9 +1972,9 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
 }
 
 // Selected inverse on the tile columns J >= jf (and the corner): Phase 1 of
-// the columns from jf - 1 on (the first Phase 2 group also starts the early
-// part of column jf - 1), Phase 2 groups N-1 .. jf.  jf = 0 is the whole
-// pattern.
+// the columns from jf - 1 on (the first Phase 2 group also holds the EA, E1A
+// and EB tasks of column jf - 1), Phase 2 groups N-1 .. jf.  jf = 0 is the
+// whole pattern.
 static int selinv_impl(const double* Lm, double* S, const stiles_layout& lay, int64_t jf, int32_t* info,
                        void* workspace, hipStream_t st) {
     Lay L = to_dev(lay);
