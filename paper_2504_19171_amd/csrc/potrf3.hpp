@@ -417,7 +417,8 @@ __device__ __forceinline__ void p3_update_dispatch(int s0, dbl4 (&nxt)[P3_SLOTS]
 // (column-major, upper part 0).  Thread 0 returns the first failing local
 // column (or -1) and the log det pair.
 //
-// Panels are announced as they are finished: *fpo is raised by one for each
+// Panels are announced as they are finished (fpo == nullptr: never, a test
+// hook of the caller): *fpo is raised by one for each
 // (agent-scope relaxed atomic add), once the off-diagonal tiles L_Ip (I > p)
 // and Y_p are in global memory, written with device-coherent stores, so a
 // kernel running concurrently on other compute units may read them with
@@ -539,10 +540,10 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
         // D, Y of p+1; panel p+1 in the pool; Dn; and the stores of panel p
         // complete, so it is announced.
         p3_bar_all();
-        if (threadIdx.x == 0) __hip_atomic_fetch_add(fpo, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0 && fpo) __hip_atomic_fetch_add(fpo, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     p3_bar_all();   // the last panel's stores complete
-    if (threadIdx.x == 0) __hip_atomic_fetch_add(fpo, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0 && fpo) __hip_atomic_fetch_add(fpo, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     // log det: 2 log L_jj in parallel, then a fixed-order compensated sum
     // (lane l of wavefront 0 sums entries l, l+64, ..., then the lanes are
     // joined pairwise by a butterfly)

@@ -286,7 +286,7 @@ struct TrSmem {
     int sh;
 };
 __device__ inline bool tr_panel(double* C, int ld, const double* Ljj, const double* Yd, int b, const int* fpo,
-                                int* ftr, const Sched& sc, TrSmem& sm) {
+                                int* ftr, const Sched& sc, TrSmem& sm, int ticket) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int np = b / 16;
@@ -369,7 +369,7 @@ __device__ inline bool tr_panel(double* C, int ld, const double* Ljj, const doub
                 else st_s(C, ci, o[r]);
             }
         }
-        if (ftr) sched_signal(sc, ftr, 0);   // waits for the stores, then a barrier
+        if (ftr) sched_signal(sc, ftr, ticket);   // waits for the stores, then a barrier
         else __syncthreads();
 #pragma unroll
         for (int t = 0; t < 4; ++t)
@@ -526,7 +526,7 @@ __device__ inline bool col_wait(const Sched& sc, const int* flag, int n, int tar
 // owns the 32 x 32 quarter (w/2, w%2), four 16 x 16 tiles; tiles past the
 // valid rows, and tiles above the diagonal of a diagonal block, are not
 // stored (a fifth wavefront's quarter lies past the block: it stores nothing).
-__device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, const Sched& sc, int* sh) {
+__device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, const Sched& sc, int* sh, int ticket) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;
     const int qi = w >> 1, qj = w & 1;
@@ -602,7 +602,7 @@ __device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, cons
                     st_coh_s(O, (uint32_t)((16 * ti + li) + (16 * tj + 4 * r + lk) * u.ldo), ov[x][y][r] - acc[x][y][r]);
             }
         }
-    if (u.cnt) sched_signal(sc, u.cnt, 0);   // waits for the stores, then a barrier
+    if (u.cnt) sched_signal(sc, u.cnt, ticket);   // waits for the stores, then a barrier
     return true;
 }
 
@@ -618,9 +618,10 @@ union ColSmem {
 // upd (single-launch factor, else nullptr): the POTRF waits until the
 // earlier columns' updates of its tile are in, a TRSM block until those of
 // its rows are; the update blocks wait for the earlier updates of their
-// targets (col_update).
+// targets (col_update).  gt: the task's ticket in the launch (the test hook
+// Sched::withhold names one whose signals are never sent).
 __device__ inline bool col_task(ColSmem& sm, int& sh, double* Lm, const Lay& L, int64_t J, double* Yd, int* cf,
-                                const Sched& st, double* ldp, int* info, int t, int* upd) {
+                                const Sched& st, double* ldp, int* info, int t, int* upd, int gt) {
     const int ntr = col_tr_blocks(L, J);
     const int nbr = L.b / 16, s = L.s(J), C64 = L.b / 64;
     int* fpo = cf + CF_PO;
@@ -634,7 +635,7 @@ __device__ inline bool col_task(ColSmem& sm, int& sh, double* Lm, const Lay& L, 
             }
             int fail;
             double ls, lc;
-            potrf3(Lm + L.band(J, 0), L.b, L.b, Yd, sm.po, &fail, &ls, &lc, fpo);
+            potrf3(Lm + L.band(J, 0), L.b, L.b, Yd, sm.po, &fail, &ls, &lc, gt == st.withhold ? nullptr : fpo);
             if (threadIdx.x == 0) {
                 ldp[0] = ls;
                 ldp[1] = lc;
@@ -658,10 +659,10 @@ __device__ inline bool col_task(ColSmem& sm, int& sh, double* Lm, const Lay& L, 
                 }
                 if (!ok) return false;
             }
-            if (!tr_panel(C, ld, Lm + L.band(J, 0), Yd, L.b, fpo, ftr + g, st, sm.tr)) return false;
+            if (!tr_panel(C, ld, Lm + L.band(J, 0), Yd, L.b, fpo, ftr + g, st, sm.tr, gt)) return false;
         } else {
             const UpBlock u = col_up_decode(Lm, L, J, t - 1 - ntr, upd);
-            if (!col_update(u, ftr, L.b / 16, st, &sh)) return false;
+            if (!col_update(u, ftr, L.b / 16, st, &sh, gt)) return false;
         }
     }
     return true;
@@ -691,7 +692,7 @@ __global__ __launch_bounds__(P3_NT) void k_factor_all(double* Lm, Lay L, double*
         }
         const int64_t J = lo;
         if (!col_task(sm, sh, Lm, L, J, Yd + J * (int64_t)L.b * 16, cf + J * cstride, sc, ldp + 2 * J, info,
-                      g - off[J], upd))
+                      g - off[J], upd, g))
             return;
     }
 }
@@ -1340,7 +1341,7 @@ __global__ __launch_bounds__(P3_NT) void kb_column(BColArgs a, int64_t J) {
         const BInst& I = a.bi[a.order[g - a.off[t]]];
         const FactorWs f = factor_ws(I.L, I.ws);
         if (!col_task(sm, sh, I.Lm, I.L, J, f.Yd + J * (int64_t)I.L.b * 16, f.cf + J * col_stride(I.L), sc,
-                      f.ldp + 2 * J, f.winfo, t, nullptr))
+                      f.ldp + 2 * J, f.winfo, t, nullptr, g))
             return;
     }
 }
@@ -1941,7 +1942,7 @@ int stiles_factor(const double* A, double* Lm, int64_t n, int64_t bandwidth, int
     sc.ticket = nullptr;
     sc.err = f.err;
     sc.spin_limit = spin_limit_ticks(di);
-    sc.withhold = -1;
+    sc.withhold = debug_withhold();
 
     if (A != Lm) {
         hipEvent_t tm = tm_begin(st);

@@ -166,15 +166,3 @@ class LogDet:
 
     def __call__(self, theta):
         return self._f.apply(theta)
-
-
-def closed_form(nt: int, ns: int, kappa: float, theta) -> Tuple[float, Tuple[float, float]]:
-    """log det and gradient of exp(theta_1) K + exp(theta_2) I (no arrow, no
-    Z^T Z) from the eigenvalues of K: lambda_t mu_s with lambda_t = 2 - 2
-    cos(pi t / n_t) and mu_s = (kappa^2 + 2 - 2 cos(pi s / n_s))^2."""
-    import numpy as np
-    lam = 2.0 - 2.0 * np.cos(np.pi * np.arange(nt) / nt)
-    mu = (kappa ** 2 + 2.0 - 2.0 * np.cos(np.pi * np.arange(ns) / ns)) ** 2
-    e1, e2 = math.exp(float(theta[0])), math.exp(float(theta[1]))
-    ev = e1 * np.outer(lam, mu) + e2
-    return float(np.log(ev).sum()), (float((e1 * np.outer(lam, mu) / ev).sum()), float((e2 / ev).sum()))

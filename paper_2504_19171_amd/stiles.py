@@ -180,6 +180,15 @@ def _stream_handle(stream) -> int:
     return int(s.cuda_stream)
 
 
+def _on(stream):
+    """Context in which the wrappers allocate their outputs and temporaries:
+    the stream the kernels are enqueued on, so the caching allocator never hands
+    a temporary's memory to other work while those kernels may still use it."""
+    import contextlib
+    import torch
+    return torch.cuda.stream(stream) if stream is not None else contextlib.nullcontext()
+
+
 def _dev_f64(x, name: str):
     import torch
     if not (isinstance(x, torch.Tensor) and x.is_cuda and x.dtype == torch.float64 and x.is_contiguous()):
@@ -189,18 +198,19 @@ def _dev_f64(x, name: str):
 
 def pack(ab, arrow_rows, corner, lay: Layout, out=None, stream=None):
     """Pack device arrays in canonical band form into a new tile buffer."""
-    import torch
-    ab = _dev_f64(ab, "ab")
-    dev = ab.device
-    if out is None:
-        out = torch.empty(lay.total_doubles, dtype=torch.float64, device=dev)
-    P = _dev_f64(arrow_rows, "arrow_rows").data_ptr() if lay.arrow else None
-    C = _dev_f64(corner, "corner").data_ptr() if lay.arrow else None
-    rc = load().stiles_pack(ab.data_ptr(), P, C, out.data_ptr(), lay.n, lay.bandwidth, lay.arrow,
-                            lay.tile, _stream_handle(stream))
-    if rc != 0:
-        raise StilesError(rc, "stiles_pack")
-    return out
+    with _on(stream):
+        import torch
+        ab = _dev_f64(ab, "ab")
+        dev = ab.device
+        if out is None:
+            out = torch.empty(lay.total_doubles, dtype=torch.float64, device=dev)
+        P = _dev_f64(arrow_rows, "arrow_rows").data_ptr() if lay.arrow else None
+        C = _dev_f64(corner, "corner").data_ptr() if lay.arrow else None
+        rc = load().stiles_pack(ab.data_ptr(), P, C, out.data_ptr(), lay.n, lay.bandwidth, lay.arrow,
+                                lay.tile, _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_pack")
+        return out
 
 
 def factor(A, lay: Layout, out=None, workspace=None, stream=None) -> Tuple[object, object, object]:
@@ -209,38 +219,40 @@ def factor(A, lay: Layout, out=None, workspace=None, stream=None) -> Tuple[objec
     ``out`` may be ``A`` itself (in place).  logdet is a 1-element float64
     tensor and info a 1-element int32 tensor; neither is synchronised.
     """
-    import torch
-    A = _dev_f64(A, "A")
-    dev = A.device
-    L = out if out is not None else torch.empty_like(A)
-    ws = workspace
-    if ws is None:
-        ws = torch.empty(lay.factor_workspace_bytes, dtype=torch.uint8, device=dev)
-    logdet = torch.empty(1, dtype=torch.float64, device=dev)
-    info = torch.empty(1, dtype=torch.int32, device=dev)
-    rc = load().stiles_factor(A.data_ptr(), L.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
-                              logdet.data_ptr(), info.data_ptr(), ws.data_ptr(), ws.numel(),
-                              _stream_handle(stream))
-    if rc != 0:
-        raise StilesError(rc, "stiles_factor")
-    return L, logdet, info
+    with _on(stream):
+        import torch
+        A = _dev_f64(A, "A")
+        dev = A.device
+        L = out if out is not None else torch.empty_like(A)
+        ws = workspace
+        if ws is None:
+            ws = torch.empty(lay.factor_workspace_bytes, dtype=torch.uint8, device=dev)
+        logdet = torch.empty(1, dtype=torch.float64, device=dev)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+        rc = load().stiles_factor(A.data_ptr(), L.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                                  logdet.data_ptr(), info.data_ptr(), ws.data_ptr(), ws.numel(),
+                                  _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_factor")
+        return L, logdet, info
 
 
 def selinv(L, lay: Layout, out=None, workspace=None, stream=None):
     """Sigma = A^{-1} on the tile pattern of L; returns (Sigma, info) on the device."""
-    import torch
-    L = _dev_f64(L, "L")
-    dev = L.device
-    S = out if out is not None else torch.empty_like(L)
-    ws = workspace
-    if ws is None:
-        ws = torch.empty(lay.selinv_workspace_bytes, dtype=torch.uint8, device=dev)
-    info = torch.empty(1, dtype=torch.int32, device=dev)
-    rc = load().stiles_selinv(L.data_ptr(), S.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
-                              info.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
-    if rc != 0:
-        raise StilesError(rc, "stiles_selinv")
-    return S, info
+    with _on(stream):
+        import torch
+        L = _dev_f64(L, "L")
+        dev = L.device
+        S = out if out is not None else torch.empty_like(L)
+        ws = workspace
+        if ws is None:
+            ws = torch.empty(lay.selinv_workspace_bytes, dtype=torch.uint8, device=dev)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+        rc = load().stiles_selinv(L.data_ptr(), S.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                                  info.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_selinv")
+        return S, info
 
 
 def timing_enable(on: bool = True) -> None:
@@ -296,20 +308,21 @@ def factor_batched(As, lays, outs=None, workspace=None, info=None, stream=None):
     ``outs[k]`` may be ``As[k]`` (in place).  ``info[:, 0]`` is each matrix's
     factor info (as :func:`factor`); column 1 is left for :func:`selinv_batched`.
     """
-    import torch
-    As = [_dev_f64(x, "A") for x in As]
-    dev = As[0].device
-    Ls = outs if outs is not None else [torch.empty_like(x) for x in As]
-    ws = workspace if workspace is not None else torch.empty(batch_workspace_bytes(lays), dtype=torch.uint8,
-                                                             device=dev)
-    logdet = torch.empty(len(As), dtype=torch.float64, device=dev)
-    if info is None:
-        info = torch.zeros((len(As), 2), dtype=torch.int32, device=dev)
-    items = _batch_items(lays, As=As, Ls=Ls, logdet=logdet, info=info)
-    rc = load().stiles_factor_batched(items, len(As), ws.data_ptr(), ws.numel(), _stream_handle(stream))
-    if rc != 0:
-        raise StilesError(rc, "stiles_factor_batched")
-    return Ls, logdet, info
+    with _on(stream):
+        import torch
+        As = [_dev_f64(x, "A") for x in As]
+        dev = As[0].device
+        Ls = outs if outs is not None else [torch.empty_like(x) for x in As]
+        ws = workspace if workspace is not None else torch.empty(batch_workspace_bytes(lays), dtype=torch.uint8,
+                                                                 device=dev)
+        logdet = torch.empty(len(As), dtype=torch.float64, device=dev)
+        if info is None:
+            info = torch.zeros((len(As), 2), dtype=torch.int32, device=dev)
+        items = _batch_items(lays, As=As, Ls=Ls, logdet=logdet, info=info)
+        rc = load().stiles_factor_batched(items, len(As), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_factor_batched")
+        return Ls, logdet, info
 
 
 def selinv_batched(Ls, lays, outs=None, workspace=None, info=None, stream=None):
@@ -317,92 +330,97 @@ def selinv_batched(Ls, lays, outs=None, workspace=None, info=None, stream=None):
 
     ``info[:, 1]`` receives each matrix's selinv info (as :func:`selinv`).
     """
-    import torch
-    Ls = [_dev_f64(x, "L") for x in Ls]
-    dev = Ls[0].device
-    Ss = outs if outs is not None else [torch.empty_like(x) for x in Ls]
-    ws = workspace if workspace is not None else torch.empty(batch_workspace_bytes(lays), dtype=torch.uint8,
-                                                             device=dev)
-    if info is None:
-        info = torch.zeros((len(Ls), 2), dtype=torch.int32, device=dev)
-    dummy = torch.empty(len(Ls), dtype=torch.float64, device=dev)
-    items = _batch_items(lays, Ls=Ls, Sigmas=Ss, logdet=dummy, info=info)
-    rc = load().stiles_selinv_batched(items, len(Ls), ws.data_ptr(), ws.numel(), _stream_handle(stream))
-    if rc != 0:
-        raise StilesError(rc, "stiles_selinv_batched")
-    return Ss, info
+    with _on(stream):
+        import torch
+        Ls = [_dev_f64(x, "L") for x in Ls]
+        dev = Ls[0].device
+        Ss = outs if outs is not None else [torch.empty_like(x) for x in Ls]
+        ws = workspace if workspace is not None else torch.empty(batch_workspace_bytes(lays), dtype=torch.uint8,
+                                                                 device=dev)
+        if info is None:
+            info = torch.zeros((len(Ls), 2), dtype=torch.int32, device=dev)
+        dummy = torch.empty(len(Ls), dtype=torch.float64, device=dev)
+        items = _batch_items(lays, Ls=Ls, Sigmas=Ss, logdet=dummy, info=info)
+        rc = load().stiles_selinv_batched(items, len(Ls), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_selinv_batched")
+        return Ss, info
 
 
 def trace_product(Sigma, B, lay: Layout, out=None, workspace=None, stream=None):
     """sum_ij Sigma_ij B_ij over the real entries of the tile pattern (a
     1-element device tensor): tr(A^{-1} B) for Sigma from :func:`selinv` and B
     packed by :func:`pack` with its pattern inside L's."""
-    import torch
-    Sigma = _dev_f64(Sigma, "Sigma")
-    B = _dev_f64(B, "B")
-    dev = Sigma.device
-    if out is None:
-        out = torch.empty(1, dtype=torch.float64, device=dev)
-    ws = workspace if workspace is not None else torch.empty(int(load().stiles_trace_workspace_bytes()),
-                                                             dtype=torch.uint8, device=dev)
-    rc = load().stiles_trace_product(Sigma.data_ptr(), B.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
-                                     out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
-    if rc != 0:
-        raise StilesError(rc, "stiles_trace_product")
-    return out
+    with _on(stream):
+        import torch
+        Sigma = _dev_f64(Sigma, "Sigma")
+        B = _dev_f64(B, "B")
+        dev = Sigma.device
+        if out is None:
+            out = torch.empty(1, dtype=torch.float64, device=dev)
+        ws = workspace if workspace is not None else torch.empty(int(load().stiles_trace_workspace_bytes()),
+                                                                 dtype=torch.uint8, device=dev)
+        rc = load().stiles_trace_product(Sigma.data_ptr(), B.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                                         out.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_trace_product")
+        return out
 
 
 def inverse(L, lay: Layout, out=None, workspace=None, stream=None):
     """Every entry of A^{-1} (n x n, column-major, full symmetric) from the factor L;
     returns (Ainv, info) on the device."""
-    import torch
-    L = _dev_f64(L, "L")
-    dev = L.device
-    n = lay.n
-    Ainv = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=dev)
-    ws = workspace
-    if ws is None:
-        ws = torch.empty(int(load().stiles_inverse_workspace_bytes(ctypes.byref(lay._c()))), dtype=torch.uint8,
-                         device=dev)
-    info = torch.empty(1, dtype=torch.int32, device=dev)
-    rc = load().stiles_inverse(L.data_ptr(), Ainv.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
-                               info.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
-    if rc != 0:
-        raise StilesError(rc, "stiles_inverse")
-    return Ainv, info
+    with _on(stream):
+        import torch
+        L = _dev_f64(L, "L")
+        dev = L.device
+        n = lay.n
+        Ainv = out if out is not None else torch.empty((n, n), dtype=torch.float64, device=dev)
+        ws = workspace
+        if ws is None:
+            ws = torch.empty(int(load().stiles_inverse_workspace_bytes(ctypes.byref(lay._c()))), dtype=torch.uint8,
+                             device=dev)
+        info = torch.empty(1, dtype=torch.int32, device=dev)
+        rc = load().stiles_inverse(L.data_ptr(), Ainv.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                                   info.data_ptr(), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_inverse")
+        return Ainv, info
 
 
 def selinv_range(L, lay: Layout, first_column: int, out=None, workspace=None, stream=None):
     """:func:`selinv` restricted to the tile columns >= first_column (and the corner)."""
-    import torch
-    L = _dev_f64(L, "L")
-    S = out if out is not None else torch.empty_like(L)
-    ws = workspace if workspace is not None else torch.empty(lay.selinv_workspace_bytes, dtype=torch.uint8,
-                                                             device=L.device)
-    info = torch.empty(1, dtype=torch.int32, device=L.device)
-    rc = load().stiles_selinv_range(L.data_ptr(), S.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
-                                    int(first_column), info.data_ptr(), ws.data_ptr(), ws.numel(),
-                                    _stream_handle(stream))
-    if rc != 0:
-        raise StilesError(rc, "stiles_selinv_range")
-    return S, info
+    with _on(stream):
+        import torch
+        L = _dev_f64(L, "L")
+        S = out if out is not None else torch.empty_like(L)
+        ws = workspace if workspace is not None else torch.empty(lay.selinv_workspace_bytes, dtype=torch.uint8,
+                                                                 device=L.device)
+        info = torch.empty(1, dtype=torch.int32, device=L.device)
+        rc = load().stiles_selinv_range(L.data_ptr(), S.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                                        int(first_column), info.data_ptr(), ws.data_ptr(), ws.numel(),
+                                        _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_selinv_range")
+        return S, info
 
 
 def gather(Sigma, lay: Layout, ij, out=None, stream=None):
     """Sigma(i, j) for the pairs ij (a (k, 2) int64 device tensor) read off the tile layout."""
-    import torch
-    Sigma = _dev_f64(Sigma, "Sigma")
-    ij = ij.contiguous()
-    if ij.dtype != torch.int64 or not ij.is_cuda or ij.dim() != 2 or ij.shape[1] != 2:
-        raise TypeError("ij must be a (k, 2) int64 CUDA tensor")
-    k = ij.shape[0]
-    if out is None:
-        out = torch.empty(k, dtype=torch.float64, device=Sigma.device)
-    rc = load().stiles_gather(Sigma.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
-                              ij.data_ptr() if k else None, k, out.data_ptr() if k else None, _stream_handle(stream))
-    if rc != 0:
-        raise StilesError(rc, "stiles_gather")
-    return out
+    with _on(stream):
+        import torch
+        Sigma = _dev_f64(Sigma, "Sigma")
+        ij = ij.contiguous()
+        if ij.dtype != torch.int64 or not ij.is_cuda or ij.dim() != 2 or ij.shape[1] != 2:
+            raise TypeError("ij must be a (k, 2) int64 CUDA tensor")
+        k = ij.shape[0]
+        if out is None:
+            out = torch.empty(k, dtype=torch.float64, device=Sigma.device)
+        rc = load().stiles_gather(Sigma.data_ptr(), lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                                  ij.data_ptr() if k else None, k, out.data_ptr() if k else None, _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_gather")
+        return out
 
 
 def selection_closure(lay: Layout, pairs):
@@ -429,12 +447,13 @@ def select(L, lay: Layout, pairs, stream=None):
     """Sigma(i, j) for a list of pairs: when they all lie in the tile pattern of L,
     the selected inverse of their closure only (stiles_selinv_range) read with
     stiles_gather; otherwise the full inverse.  Returns (values, info) on the device."""
-    import numpy as np
-    import torch
-    inside, first = selection_closure(lay, pairs)
-    ij = torch.as_tensor(np.asarray(pairs, dtype=np.int64).reshape(-1, 2), device=L.device)
-    if inside:
-        S, info = selinv_range(L, lay, first, stream=stream)
-        return gather(S, lay, ij, stream=stream), info
-    X, info = inverse(L, lay, stream=stream)
-    return X.t()[ij[:, 0], ij[:, 1]], info
+    with _on(stream):
+        import numpy as np
+        import torch
+        inside, first = selection_closure(lay, pairs)
+        ij = torch.as_tensor(np.asarray(pairs, dtype=np.int64).reshape(-1, 2), device=L.device)
+        if inside:
+            S, info = selinv_range(L, lay, first, stream=stream)
+            return gather(S, lay, ij, stream=stream), info
+        X, info = inverse(L, lay, stream=stream)
+        return X.t()[ij[:, 0], ij[:, 1]], info

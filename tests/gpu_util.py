@@ -4,7 +4,7 @@ import math
 import numpy as np
 
 from paper_2504_19171_amd import inputs
-from paper_2504_19171_amd import layout as lo
+import tile_layout as lo
 from paper_2504_19171_amd import stiles as st
 
 # Tolerances (stated for the hot path): Sigma entries within 1e-10 relative,

@@ -7,7 +7,7 @@ import numpy as np
 import pytest
 
 from paper_2504_19171_amd import inputs
-from paper_2504_19171_amd import layout as lo
+import tile_layout as lo
 from paper_2504_19171_amd import stiles as st
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))

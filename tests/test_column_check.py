@@ -6,7 +6,7 @@ import types
 import numpy as np
 
 from paper_2504_19171_amd import inputs
-from paper_2504_19171_amd import layout as lo
+import tile_layout as lo
 from paper_2504_19171_amd import stiles as st
 from gpu_util import column_errors, L_TOL, SIGMA_TOL
 

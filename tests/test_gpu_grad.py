@@ -8,6 +8,7 @@ import math
 import numpy as np
 import pytest
 
+from closed_form import closed_form
 from paper_2504_19171_amd import grad, inputs
 
 pytestmark = pytest.mark.gpu
@@ -79,7 +80,7 @@ def test_full_size_arrow_free_closed_form(torch_cuda):
         print(f"full size arrow-free theta {theta0}: n = {m.n}, w = {m.w}", flush=True)
         ld = fn(theta)
         ld.backward()
-        ref, gref = grad.closed_form(nt, ns, kappa, theta0)
+        ref, gref = closed_form(nt, ns, kappa, theta0)
         g = theta.grad.tolist()
         print(f"  log det {float(ld):.13e} closed form {ref:.13e}; grad {g} closed form {gref}", flush=True)
         assert abs(float(ld) - ref) <= 1e-12 * max(1.0, abs(ref))

@@ -5,7 +5,7 @@ import numpy as np
 import pytest
 
 from paper_2504_19171_amd import inputs
-from paper_2504_19171_amd import layout as lo
+import tile_layout as lo
 
 pytestmark = pytest.mark.gpu
 

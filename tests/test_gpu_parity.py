@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from paper_2504_19171_amd import inputs
-from paper_2504_19171_amd import layout as lo
+import tile_layout as lo
 
 pytestmark = pytest.mark.gpu
 
@@ -168,3 +168,29 @@ def test_watchdog_turns_a_missing_signal_into_an_error(torch_cuda, monkeypatch):
     S, sinfo = st.selinv(L, lay)      # and the next call is clean again
     torch.cuda.synchronize()
     assert int(sinfo.item()) == 0
+
+
+def test_factor_watchdog_turns_a_missing_signal_into_an_error(torch_cuda, monkeypatch):
+    """The factor's first task (the POTRF of tile column 0) never announces its
+    panels (host-side test hook); the waits of the TRSM and update tasks and of
+    the next POTRF expire, every workgroup leaves, and info is STILES_ETIMEOUT
+    with log det NaN.  The next call is clean again."""
+    import torch
+    from gpu_util import to_device
+    from paper_2504_19171_amd import stiles as st
+    M = inputs.arrowhead_spd(700, 60, 10, seed=4)
+    lay = st.layout(M.n, 60, 10, 64)
+    A = st.pack(*to_device(M, "cuda:0"), lay)
+    torch.cuda.synchronize()
+    monkeypatch.setenv("STILES_DEBUG_WITHHOLD", "0")
+    monkeypatch.setenv("STILES_SPIN_LIMIT_MS", "20")
+    print("factor watchdog: withholding ticket 0", flush=True)
+    L, logdet, info = st.factor(A, lay)
+    torch.cuda.synchronize()
+    assert int(info.item()) == st.STILES_ETIMEOUT
+    assert math.isnan(float(logdet.item()))
+    monkeypatch.delenv("STILES_DEBUG_WITHHOLD")
+    monkeypatch.delenv("STILES_SPIN_LIMIT_MS")
+    L2, logdet2, info2 = st.factor(A, lay)
+    torch.cuda.synchronize()
+    assert int(info2.item()) == 0 and math.isfinite(float(logdet2.item()))

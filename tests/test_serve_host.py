@@ -31,8 +31,23 @@ def test_admission_caps_the_batch():
     assert serve.admit(jobs([5]), 4, 3) == []
 
 
-def test_job_bytes_cover_results_and_workspace():
+def test_admission_charges_the_workspace_growth():
+    """A lane holding a workspace of 12 bytes; a batch of k jobs needs 10 k of
+    workspace: the growth beyond 12 counts against the room."""
+    held = 12
+    growth = lambda batch: max(0, 10 * len(batch) - held)
+    q = jobs([5, 5, 5, 5])
+    # 1 job: 5 + 0; 2 jobs: 10 + 8 = 18; 3 jobs: 15 + 18 = 33 > 30
+    batch = serve.admit(q, 30, 8, growth)
+    assert [j.jid for j in batch] == [0, 1]
+    # a lane with nothing held: the first job alone needs 5 + 10 = 15
+    held = 0
+    assert serve.admit(jobs([5]), 14, 8, growth) == []
+
+
+def test_job_bytes_cover_results_and_input():
     from paper_2504_19171_amd import stiles as st
     lay = st.layout(20000, 128, 40, 128)
     nbytes = serve.job_bytes(lay)
-    assert nbytes >= 2 * 8 * lay.total_doubles + lay.selinv_workspace_bytes
+    inp = 8 * (129 * lay.nb + 40 * lay.nb + 40 * 40)
+    assert nbytes == 2 * 8 * lay.total_doubles + inp

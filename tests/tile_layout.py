@@ -1,4 +1,5 @@
-"""Host-side index maps of the tile layout (numpy; no arithmetic of the method).
+"""Host-side index maps of the tile layout, for the tests (numpy; no arithmetic
+of the method).  Test infrastructure: the product library never uses it.
 
 The tile layout is described in ``include/stiles.h``.  These helpers move
 entries between it and the canonical band form used by the input generator:
