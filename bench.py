@@ -47,26 +47,59 @@ PEAK_HBM_GBS = 8000.0
 
 
 def kernel_flops(nb, w, a, b):
-    """Algorithmic flops per step for each timing kind of the library."""
+    """Algorithmic flops per step for each timing kind of the library.  The
+    diagonal-tile POTRFs, panel TRSMs and trailing updates of the band all run
+    inside the factor's single launch (kind "factor"); kind "potrf" is the
+    corner's Cholesky alone (its own launch)."""
     from paper_2504_19171_amd import flops as fl
     N, B = fl._halfband(nb, w, b)
+    ap = -(-a // 16) * 16
     k = dict(potrf=0.0, trsm=0.0, update=0.0, phase1=0.0, phase2=0.0, factor=0.0, other=0.0)
     for J in range(N):
         s = min(B, N - 1 - J)
         m = s * b + a
-        k["potrf"] += b ** 3 / 3
-        k["trsm"] += m * b * b
-        k["update"] += m * m * b
         k["phase1"] += b ** 3 / 3 + m * b * b + b ** 3 / 3
         k["phase2"] += 2 * m * m * b + m * b * b
         k["factor"] += b ** 3 / 3 + m * b * b + m * m * b   # the factor's single launch (k_factor_all)
-    k["other"] += a ** 3 / 3          # corner factor
+    if ap <= 256:
+        k["potrf"] += a ** 3 / 3          # corner factor: one POTRF launch
+    else:
+        k["potrf"] += 256 ** 3 / 3 + (a - 256) ** 3 / 3   # its two diagonal blocks; TRSM + SYRK in "other"
+        k["other"] += (a - 256) * 256 ** 2 + (a - 256) ** 2 * 256
     k["phase1"] += 2 * a ** 3 / 3     # corner TRTRI + LAUUM
     return k
 
 
-def cpu_baseline(w, a, b, nb_sample, seed):
-    """The oracle (as it stands) on a shorter matrix of the same w, a, b."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+_ORACLE_ONE = r"""
+import sys, time, json
+sys.path.insert(0, sys.argv[1])
+import oracle
+from paper_2504_19171_amd import inputs
+nb, w, a, b, seed = (int(x) for x in sys.argv[2:7])
+M = inputs.arrowhead_spd(nb, w, a, seed=seed)
+t0 = time.perf_counter()
+f = oracle.cholesky(M.ab, M.P, M.C)
+oracle.selinv(f, b)
+print(json.dumps({"seconds": time.perf_counter() - t0, "threads": oracle.num_threads()}))
+"""
+
+
+def cpu_baseline(w, a, b, nb_sample, seed, nb_single):
+    """The oracle (as it stands) on the host cores: on all of them (OpenMP) over
+    nb_sample band rows, and on one core over nb_single band rows (a child
+    process with OMP_NUM_THREADS=1), with the same w, a, b as the workload."""
+    import subprocess
     import oracle
     from paper_2504_19171_amd import flops as fl
     from paper_2504_19171_amd import inputs
@@ -75,16 +108,29 @@ def cpu_baseline(w, a, b, nb_sample, seed):
     f = oracle.cholesky(M.ab, M.P, M.C)
     oracle.selinv(f, b)
     dt = time.perf_counter() - t0
+    del M, f
     flop = fl.factor_flops(nb_sample, w, a, b) + fl.selinv_flops(nb_sample, w, a, b)
-    return {"value": round(flop / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
-            "kind": "oracle", "seconds": round(dt, 3),
-            "sample": f"n = {nb_sample:,} + {a}, w = {w}, tile {b} (same band, arrow and tile as the "
-                      f"workload, {nb_sample / WORK['nb']:.0%} of its length); factor + selected inverse"}
+    out = {"value": round(flop / dt / 1e9, 3), "unit": "GFLOP/s", "cores": oracle.num_threads(),
+           "kind": "oracle", "seconds": round(dt, 3), "cpu_model": cpu_model(),
+           "sample": f"n = {nb_sample:,} + {a}, w = {w}, tile {b} (same band, arrow and tile as the "
+                     f"workload, {nb_sample / WORK['nb']:.0%} of its length); factor + selected inverse"}
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    res = subprocess.run([sys.executable, "-c", _ORACLE_ONE, ROOT, str(nb_single), str(w), str(a), str(b),
+                          str(seed)], capture_output=True, text=True, env=env, timeout=600)
+    if res.returncode == 0:
+        one = json.loads(res.stdout.strip().splitlines()[-1])
+        fl1 = fl.factor_flops(nb_single, w, a, b) + fl.selinv_flops(nb_single, w, a, b)
+        out["single_thread"] = {"value": round(fl1 / one["seconds"] / 1e9, 3), "unit": "GFLOP/s",
+                                "cores": one["threads"], "seconds": round(one["seconds"], 3),
+                                "sample": f"n = {nb_single:,} + {a}, w = {w}, tile {b}"}
+    else:
+        out["single_thread"] = {"error": res.stderr[-400:]}
+    return out
 
 
 WORKLOADS = {
-    "large": dict(nb=100000, w=1024, a=100, b=256, seed=1, cpu_nb=100000),
-    "small": dict(nb=2000, w=32, a=20, b=64, seed=0, cpu_nb=2000),
+    "large": dict(nb=100000, w=1024, a=100, b=256, seed=1, cpu_nb=100000, cpu_nb1=12000),
+    "small": dict(nb=2000, w=32, a=20, b=64, seed=0, cpu_nb=2000, cpu_nb1=2000),
     "batched": dict(),
     "served": dict(),
     "grad": dict(),
@@ -98,7 +144,8 @@ def main() -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="large")
+    ap.add_argument("--workload", choices=sorted(WORKLOADS), default="large",
+                    help="large (default, the benchmark line), or one other workload alone")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--tile", type=int, default=0, help="batched: this tile size instead of the autotuner's")
     ap.add_argument("--calib-copy", action="store_true",
@@ -110,6 +157,9 @@ def main() -> int:
     ap.add_argument("--max-batch", type=int, default=8, help="served: jobs per batch at most")
     ap.add_argument("--no-plain", action="store_true",
                     help="batched: skip the plain-form timing and the per-matrix comparison (profiling runs)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="large: skip the small, batched and served summaries of the default line")
+    ap.add_argument("--extra-jobs", type=int, default=200, help="large: jobs of the served summary")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -122,6 +172,10 @@ def main() -> int:
         return main_served(args)
     if args.workload == "grad":
         return main_grad(args)
+    if args.workload == "small":
+        r = leg_small()
+        print(json.dumps(r), flush=True)
+        return 0 if r["ok"] else 1
 
     import numpy as np
     import torch
@@ -200,10 +254,23 @@ def main() -> int:
                      "tflops": round(kf[k] / (v[0] / args.steps / 1e3) / 1e12, 3) if v[0] > 0 and kf[k] else None}
                  for k, v in per_kind.items()}
 
+    extras = {}
+    if not args.no_extras and args.workload == "large":
+        del L, S, wsf, wss, ab, P, C
+        torch.cuda.empty_cache()
+        _log("bench: small workload (latency)")
+        extras["small"] = leg_small()
+        _log(f"bench: small {extras['small']}")
+        _log("bench: batched workload (bounded: 3 timed passes)")
+        extras["batched"] = leg_batched(3, 1, device_inputs=True, log=_log)
+        _log(f"bench: served workload (bounded: the first {args.extra_jobs} jobs)")
+        extras["served"] = leg_served(args.extra_jobs, fracs=(0.5, 0.8), log=_log)
+        ok = ok and extras["small"]["ok"] and extras["batched"]["ok"] and extras["served"]["ok"]
+
     cpu = None
     if not args.no_cpu_baseline:
         print("bench: timing the CPU oracle on a sample", file=sys.stderr, flush=True)
-        cpu = cpu_baseline(w, a, b, WORK["cpu_nb"], WORK["seed"])
+        cpu = cpu_baseline(w, a, b, WORK["cpu_nb"], WORK["seed"], WORK["cpu_nb1"])
 
     srt = sorted(step_ms)
     out = {
@@ -232,15 +299,18 @@ def main() -> int:
         "cpu_baseline": cpu,
         "kernels": breakdown,
     }
+    out.update(extras)
     print(json.dumps(out), flush=True)
     return 0 if ok else 1
 
 
-def main_batched(args) -> int:
-    """64 uneven matrices (inputs.BATCH): the tile size picked by the
-    autotuner, then K timed passes of pack + batched factor + batched selinv,
-    against the plain form (each matrix alone, its own launches) on the same
-    matrices, at the batch's tile size and at each matrix's fastest one."""
+def leg_batched(steps, warmup, tile=0, plain=True, device_inputs=False, log=print):
+    """64 uneven matrices (inputs.batch_shapes): the tile size picked by the
+    autotuner, then `steps` timed passes of pack + batched factor + batched
+    selinv, against the plain form (each matrix alone, its own launches) on the
+    same matrices, at the batch's tile size and at each matrix's fastest one.
+    device_inputs: draw the matrices on the device from their seeds (the same
+    construction, a different random stream) instead of on the host."""
     import numpy as np
     import torch
     from paper_2504_19171_amd import autotune
@@ -253,49 +323,49 @@ def main_batched(args) -> int:
     shapes = inputs.batch_shapes()
     mats, nws = [], []
     for nb, w, a, seed in shapes:
-        M = inputs.arrowhead_spd(nb, w, a, seed=seed)
-        mats.append((torch.from_numpy(M.ab).to(dev), torch.from_numpy(M.P).to(dev) if a else None,
-                     torch.from_numpy(M.C).to(dev) if a else None))
-        nws.append((M.n, w, a))
+        if device_inputs:
+            mats.append(inputs.arrowhead_spd_device(nb, w, a, seed, dev))
+        else:
+            M = inputs.arrowhead_spd(nb, w, a, seed=seed)
+            mats.append((torch.from_numpy(M.ab).to(dev), torch.from_numpy(M.P).to(dev) if a else None,
+                         torch.from_numpy(M.C).to(dev) if a else None))
+        nws.append((nb + a, w, a))
     torch.cuda.synchronize()
-    print(f"bench: {len(shapes)} matrices ready in {time.perf_counter() - t0:.1f} s "
-          f"(n {min(s[0] for s in shapes)}..{max(s[0] for s in shapes)}, w in {{32, 128, 512}})",
-          file=sys.stderr, flush=True)
+    log(f"bench: {len(shapes)} matrices ready in {time.perf_counter() - t0:.1f} s "
+        f"(n {min(s[0] for s in shapes)}..{max(s[0] for s in shapes)}, w in {{32, 128, 512}})")
 
-    if args.tile:
-        tile, tune_ms = args.tile, None
+    if tile:
+        tune_ms = None
     else:
         tile, tune_ms = autotune.tune_batch(mats, nws)
-        print(f"bench: autotuner ms per batched pass {tune_ms} -> tile {tile}", file=sys.stderr, flush=True)
+        log(f"bench: autotuner ms per batched pass {tune_ms} -> tile {tile}")
     plain_same = plain_best = None
-    if not args.no_plain:
-        plain = {b: autotune.time_plain(mats, nws, b) for b in autotune.CANDIDATES}
-        plain_same = sum(plain[tile]) if tile in plain else sum(autotune.time_plain(mats, nws, tile))
-        plain_best = sum(min(plain[b][k] for b in plain) for k in range(len(shapes)))
-        print(f"bench: plain ms per pass {[(b, round(sum(v), 1)) for b, v in plain.items()]}", file=sys.stderr,
-              flush=True)
+    if plain:
+        pt = {b: autotune.time_plain(mats, nws, b) for b in autotune.CANDIDATES}
+        plain_same = sum(pt[tile]) if tile in pt else sum(autotune.time_plain(mats, nws, tile))
+        plain_best = sum(min(pt[b][k] for b in pt) for k in range(len(shapes)))
+        log(f"bench: plain ms per pass {[(b, round(sum(v), 1)) for b, v in pt.items()]}")
 
     _, buf = autotune.time_batched(mats, nws, tile)
-    for i in range(args.warmup):
+    for i in range(warmup):
         autotune.run_batched(buf)
     torch.cuda.synchronize()
     stream = torch.cuda.current_stream()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(args.steps + 1)]
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     st.timing_enable(True)
     ev[0].record(stream)
-    for i in range(args.steps):
+    for i in range(steps):
         ld, info = autotune.run_batched(buf)
         ev[i + 1].record(stream)
     torch.cuda.synchronize()
     per_kind = st.timing_collect()
     st.timing_enable(False)
-    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(args.steps)]
-    total_ms = ev[0].elapsed_time(ev[-1])
-    ms_step = total_ms / args.steps
+    step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
+    ms_step = ev[0].elapsed_time(ev[-1]) / steps
 
     # every matrix: batched result == single-matrix result, bit for bit
-    same = None if args.no_plain else True
-    for k, ((ab, P, C), lay) in enumerate(zip(mats, buf["lays"]) if not args.no_plain else []):
+    same = None if not plain else True
+    for k, ((ab, P, C), lay) in enumerate(zip(mats, buf["lays"]) if plain else []):
         A = st.pack(ab, P, C, lay)
         L, ld1, _ = st.factor(A, lay)
         S, _ = st.selinv(L, lay)
@@ -303,46 +373,62 @@ def main_batched(args) -> int:
         same &= float(ld1.item()) == float(ld[k].item())
         del A, L, S
     ok = bool((info.cpu().numpy() == 0).all()) and bool(torch.isfinite(ld).all()) and same is not False
-
     flop = sum(fl.factor_flops(n - a, w, a, tile) + fl.selinv_flops(n - a, w, a, tile) for (n, w, a) in nws)
-    value = flop / (ms_step / 1e3) / 1e9
     srt = sorted(step_ms)
-    kinds = {k: {"ms_per_step": round(v[0] / args.steps, 3), "launches_per_step": v[1] // max(args.steps, 1)}
-             for k, v in per_kind.items() if v[1]}
-    out = {
-        "metric": METRIC,
-        "value": round(value, 3),
-        "unit": "GFLOP/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 4),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"batched: {len(shapes)} matrices, band order uniform on [5,000, 50,000], "
-                               "half-bandwidth in {32, 128, 512}, arrow uniform on [10, 200], seeded N(0,1) "
-                               "band and arrow, diagonal = row |sum| + 1",
-                   "instances": len(shapes), "tile": tile, "autotune_ms": tune_ms,
-                   "step": "pack + batched factor (L, log det) + batched selinv, all matrices",
-                   "flops_per_step": flop},
+    del buf, mats
+    torch.cuda.empty_cache()
+    return {
+        "instances": len(shapes), "tile": tile, "autotune_ms": tune_ms,
+        "inputs": "drawn on the device" if device_inputs else "drawn on the host",
+        "ms_per_pass": round(ms_step, 4), "gflops": round(flop / (ms_step / 1e3) / 1e9, 3),
+        "flops_per_pass": flop,
         "solves_per_s": round(len(shapes) * 1e3 / ms_step, 3),
+        "pass_ms_p50": round(srt[len(srt) // 2], 4), "pass_ms_p99": round(srt[min(len(srt) - 1, int(0.99 * len(srt)))], 4),
         "plain": None if plain_same is None else {
             "ms_same_tile": round(plain_same, 3), "ms_best_tile_each": round(plain_best, 3),
             "solves_per_s_same_tile": round(len(shapes) * 1e3 / plain_same, 3),
             "solves_per_s_best_tile_each": round(len(shapes) * 1e3 / plain_best, 3)},
         "speedup_vs_plain": None if plain_same is None else {
             "same_tile": round(plain_same / ms_step, 2), "best_tile_each": round(plain_best / ms_step, 2)},
-        "latency_ms_p50": round(srt[len(srt) // 2], 4),
-        "latency_ms_p99": round(srt[min(len(srt) - 1, int(0.99 * len(srt)))], 4),
-        "ok": ok,
         "bitwise_equal_to_single": same,
-        "kernels": kinds,
+        "kernels": {k: {"ms_per_pass": round(v[0] / steps, 3), "launches_per_pass": v[1] // max(steps, 1)}
+                    for k, v in per_kind.items() if v[1]},
+        "ok": ok,
+    }
+
+
+def main_batched(args) -> int:
+    r = leg_batched(args.steps, args.warmup, tile=args.tile, plain=not args.no_plain, log=_log)
+    out = {
+        "metric": METRIC,
+        "value": r["gflops"],
+        "unit": "GFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": r["ms_per_pass"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"batched: {r['instances']} matrices, band order uniform on [5,000, 50,000], "
+                               "half-bandwidth in {32, 128, 512}, arrow uniform on [10, 200], seeded N(0,1) "
+                               "band and arrow, diagonal = row |sum| + 1",
+                   "instances": r["instances"], "tile": r["tile"], "autotune_ms": r["autotune_ms"],
+                   "step": "pack + batched factor (L, log det) + batched selinv, all matrices",
+                   "flops_per_step": r["flops_per_pass"]},
+        "solves_per_s": r["solves_per_s"],
+        "plain": r["plain"],
+        "speedup_vs_plain": r["speedup_vs_plain"],
+        "latency_ms_p50": r["pass_ms_p50"],
+        "latency_ms_p99": r["pass_ms_p99"],
+        "ok": r["ok"],
+        "bitwise_equal_to_single": r["bitwise_equal_to_single"],
+        "kernels": r["kernels"],
     }
     print(json.dumps(out), flush=True)
-    return 0 if ok else 1
+    return 0 if r["ok"] else 1
 
 
 def main_grad(args) -> int:
@@ -420,11 +506,14 @@ def main_grad(args) -> int:
     return 0 if ok else 1
 
 
-def main_served(args) -> int:
-    """A Poisson stream of factor + selinv jobs (inputs.SERVE shapes) through
-    the serving loop (paper_2504_19171_amd/serve.py) and through the plain
-    FIFO (one job at a time), at 0.5 and 0.8 of the plain FIFO's capacity
-    measured on a prefix of the stream; p50/p99 latency and solves/s."""
+def leg_served(njobs, tile=0, budget_gb=64.0, lanes=3, max_batch=8, fracs=(0.5, 0.8, 1.5), log=print):
+    """A Poisson stream of the first `njobs` factor + selinv jobs of the served
+    workload (inputs.serve_shapes) through the serving loop
+    (paper_2504_19171_amd/serve.py) and through the plain FIFO (one job at a
+    time), at fractions of the plain FIFO's capacity measured on a prefix of
+    the stream; p50/p99 latency and solves/s.  Each job's matrix is drawn on
+    the device from its seed when the job is admitted (its upload), and
+    dropped once packed: the stream never holds more than the running jobs."""
     import numpy as np
     import torch
     from paper_2504_19171_amd import autotune
@@ -432,35 +521,39 @@ def main_served(args) -> int:
     from paper_2504_19171_amd import serve
 
     dev = torch.device("cuda:0")
-    t0 = time.perf_counter()
-    shapes = inputs.serve_shapes(args.jobs)
-    mats = [inputs.arrowhead_spd_device(nb, w, a, seed, dev) for (nb, w, a, seed) in shapes]
-    torch.cuda.synchronize()
-    print(f"bench: {len(shapes)} jobs drawn on the device in {time.perf_counter() - t0:.1f} s "
-          f"(n {min(s[0] + s[2] for s in shapes)}..{max(s[0] + s[2] for s in shapes)})", file=sys.stderr, flush=True)
-    if args.tile:
-        tile, tune_ms = args.tile, None
+    shapes = inputs.serve_shapes(njobs)
+    log(f"bench: served stream of {len(shapes)} jobs (n {min(s[0] + s[2] for s in shapes)}.."
+        f"{max(s[0] + s[2] for s in shapes)})")
+    if tile:
+        tune_ms = None
     else:
         k = min(16, len(shapes))
-        tile, tune_ms = autotune.tune_batch(mats[:k], [(nb + a, w, a) for (nb, w, a, _) in shapes[:k]])
-        print(f"bench: autotuner on the first {k} jobs {tune_ms} -> tile {tile}", file=sys.stderr, flush=True)
+        mats = [inputs.arrowhead_spd_device(nb, w, a, seed, dev) for (nb, w, a, seed) in shapes[:k]]
+        tile, tune_ms = autotune.tune_batch(mats, [(nb + a, w, a) for (nb, w, a, _) in shapes[:k]])
+        del mats
+        torch.cuda.empty_cache()
+        log(f"bench: autotuner on the first {k} jobs {tune_ms} -> tile {tile}")
 
     def jobs_at(arrivals):
-        return [serve.Job(k, nb, w, a, float(t), ab=m[0], P=m[1], C=m[2])
-                for k, ((nb, w, a, _), m, t) in enumerate(zip(shapes, mats, arrivals))]
+        return [serve.Job(k, nb, w, a, float(t),
+                          make=(lambda nb=nb, w=w, a=a, seed=seed: inputs.arrowhead_spd_device(nb, w, a, seed, dev)))
+                for k, ((nb, w, a, seed), t) in enumerate(zip(shapes, arrivals))]
+
+    def server():
+        return serve.Server(budget=int(budget_gb * 2**30), tile=tile, lanes=lanes, max_batch=max_batch)
 
     # capacities: a prefix of the stream, all arrived at 0
     npre = min(40, len(shapes))
     done = serve.serve_plain(jobs_at([0.0] * npre)[:npre], tile)
     mu = npre / max(j.done for j in done)
-    srv = serve.Server(budget=int(args.budget_gb * 2**30), tile=tile, lanes=args.lanes, max_batch=args.max_batch)
+    srv = server()
     done = srv.run(jobs_at([0.0] * npre)[:npre])
+    srv.close()
     mu_served = npre / max(j.done for j in done)
-    print(f"bench: capacity on the first {npre} jobs: plain FIFO {mu:.2f} jobs/s, served {mu_served:.2f} jobs/s",
-          file=sys.stderr, flush=True)
+    log(f"bench: capacity on the first {npre} jobs: plain FIFO {mu:.2f} jobs/s, served {mu_served:.2f} jobs/s")
     rates = {}
     ok = True
-    for frac in (0.5, 0.8, 1.5):
+    for frac in fracs:
         rng = np.random.default_rng(33)
         arr = np.cumsum(rng.exponential(1.0 / (frac * mu), len(shapes)))
         arr -= arr[0]
@@ -468,9 +561,9 @@ def main_served(args) -> int:
         for form in ("served", "plain"):
             jobs = jobs_at(arr)
             if form == "served":
-                srv = serve.Server(budget=int(args.budget_gb * 2**30), tile=tile, lanes=args.lanes,
-                                   max_batch=args.max_batch)
+                srv = server()
                 out = srv.run(jobs)
+                srv.close()
             else:
                 out = serve.serve_plain(jobs, tile)
             lat = np.array([j.done - j.arrival for j in out]) * 1e3
@@ -479,18 +572,29 @@ def main_served(args) -> int:
             res[form] = {"latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
                          "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
                          "solves_per_s": round(len(out) / span, 3)}
+            if form == "served":
+                res[form]["peak_bytes_held"] = srv.peak
             for j in jobs:
                 j.L = j.Sigma = None
             torch.cuda.synchronize()
-            print(f"bench: {form} at {frac} x capacity: {res[form]}", file=sys.stderr, flush=True)
+            log(f"bench: {form} at {frac} x capacity: {res[form]}")
         rates[str(frac)] = dict(qps=round(frac * mu, 3), **res)
-    top = rates["0.8"]["served"]
+    return {"jobs": len(shapes), "tile": tile, "autotune_ms": tune_ms, "lanes": lanes, "max_batch": max_batch,
+            "budget_gb": budget_gb, "rates_are_fractions_of": "the plain FIFO's capacity",
+            "capacity_jobs_per_s": {"plain_fifo": round(mu, 3), "served": round(mu_served, 3), "on_jobs": npre},
+            "rates": rates, "ok": bool(ok)}
+
+
+def main_served(args) -> int:
+    r = leg_served(args.jobs, tile=args.tile, budget_gb=args.budget_gb, lanes=args.lanes,
+                   max_batch=args.max_batch, log=_log)
+    top = r["rates"]["0.8"]["served"]
     out = {
         "metric": METRIC,
         "value": top["solves_per_s"],
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": len(shapes),
+        "steps": r["jobs"],
         "warmup": 0,
         "ms_per_step": round(1e3 / top["solves_per_s"], 4),
         "higher_is_better": True,
@@ -498,20 +602,69 @@ def main_served(args) -> int:
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": f"served: {len(shapes)} jobs of a Poisson stream, n log-uniform on [2,000, 200,000], "
+        "config": {"workload": f"served: {r['jobs']} jobs of a Poisson stream, n log-uniform on [2,000, 200,000], "
                                "half-bandwidth log-uniform on [16, 1,024], arrow uniform on [0, 500], seeded N(0,1) "
-                               "band and arrow drawn on the device, diagonal = row |sum| + 1",
-                   "jobs": len(shapes), "tile": tile, "autotune_ms": tune_ms, "lanes": args.lanes,
-                   "max_batch": args.max_batch, "budget_gb": args.budget_gb,
-                   "rates_are_fractions_of": "the plain FIFO's capacity"},
-        "capacity_jobs_per_s": {"plain_fifo": round(mu, 3), "served": round(mu_served, 3), "on_jobs": npre},
+                               "band and arrow drawn on the device at admission, diagonal = row |sum| + 1",
+                   "jobs": r["jobs"], "tile": r["tile"], "autotune_ms": r["autotune_ms"], "lanes": r["lanes"],
+                   "max_batch": r["max_batch"], "budget_gb": r["budget_gb"],
+                   "rates_are_fractions_of": r["rates_are_fractions_of"]},
+        "capacity_jobs_per_s": r["capacity_jobs_per_s"],
         "latency_ms_p50": top["latency_ms_p50"],
         "latency_ms_p99": top["latency_ms_p99"],
-        "rates": rates,
-        "ok": bool(ok),
+        "rates": r["rates"],
+        "ok": r["ok"],
     }
     print(json.dumps(out), flush=True)
-    return 0 if ok else 1
+    return 0 if r["ok"] else 1
+
+
+def leg_small(reps=200, warmup=20):
+    """The small workload (n = 2,000 + 20, w = 32, tile 64, seed 0), a latency
+    case: `reps` solves of pack + factor + selinv one after another, each
+    bracketed by HIP events; microseconds per solve and solves/s."""
+    import numpy as np
+    import torch
+    from paper_2504_19171_amd import inputs
+    from paper_2504_19171_amd import stiles as st
+    W = WORKLOADS["small"]
+    nb, w, a, b = W["nb"], W["w"], W["a"], W["b"]
+    dev = torch.device("cuda:0")
+    M = inputs.arrowhead_spd(nb, w, a, seed=W["seed"])
+    lay = st.layout(M.n, w, a, b)
+    ab = torch.from_numpy(M.ab).to(dev)
+    P = torch.from_numpy(M.P).to(dev)
+    C = torch.from_numpy(M.C).to(dev)
+    L = torch.empty(lay.total_doubles, dtype=torch.float64, device=dev)
+    S = torch.empty_like(L)
+    wsf = torch.empty(lay.factor_workspace_bytes, dtype=torch.uint8, device=dev)
+    wss = torch.empty(lay.selinv_workspace_bytes, dtype=torch.uint8, device=dev)
+
+    def step():
+        st.pack(ab, P, C, lay, out=L)
+        _, ld, info = st.factor(L, lay, out=L, workspace=wsf)
+        _, sinfo = st.selinv(L, lay, out=S, workspace=wss)
+        return ld, info, sinfo
+    for _ in range(warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2 * reps)]
+    stream = torch.cuda.current_stream()
+    for i in range(reps):
+        ev[2 * i].record(stream)
+        ld, info, sinfo = step()
+        ev[2 * i + 1].record(stream)
+    torch.cuda.synchronize()
+    us = sorted(1e3 * ev[2 * i].elapsed_time(ev[2 * i + 1]) for i in range(reps))
+    span_ms = ev[0].elapsed_time(ev[-1])
+    ok = int(info.item()) == 0 and int(sinfo.item()) == 0 and bool(np.isfinite(float(ld.item())))
+    return {"workload": f"small: n = {nb:,} + {a}, half-bandwidth {w}, arrow {a}, tile {b}, seed {W['seed']}",
+            "reps": reps, "warmup": warmup, "us_per_solve_p50": round(us[len(us) // 2], 2),
+            "us_per_solve_p99": round(us[min(len(us) - 1, int(0.99 * len(us)))], 2),
+            "solves_per_s": round(reps * 1e3 / span_ms, 2), "ok": bool(ok)}
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
 
 
 if __name__ == "__main__":

@@ -11,6 +11,19 @@ overlaps the running batches.  Each job's L and Sigma stay on the device
 while they are held.  Results do not depend on the mix: every matrix of a
 batch comes out as from the single-matrix calls, bit for bit.
 
+The budget counts every device buffer the server holds:
+  * each job's results (L, factored in place over its packed input, and
+    Sigma) and its input in canonical band form, from admission until the
+    results are released;
+  * each lane's batch workspace, while the lane holds it: a batch is admitted
+    only if its results plus the growth of the lane's workspace fit, and idle
+    lanes give their workspaces back when the head of the queue would not fit
+    otherwise.
+
+A job's input is either given (device tensors) or made on the lane's stream
+when the job is admitted (`Job.make`, e.g. drawn on the device from its seed),
+and dropped once packed.
+
 Host logic only (admission, queue, clocks); every step of the computation
 runs in the library's HIP kernels.
 """
@@ -25,7 +38,8 @@ from . import stiles as st
 
 @dataclass
 class Job:
-    """One request: the matrix in canonical band form on the device."""
+    """One request: the matrix in canonical band form on the device, given
+    (ab, P, C) or made at admission by `make()` -> (ab, P, C)."""
     jid: int
     nb: int
     w: int
@@ -34,13 +48,14 @@ class Job:
     ab: object = None              # device tensors (inputs)
     P: object = None
     C: object = None
+    make: Optional[Callable[[], tuple]] = None
     lay: Optional[st.Layout] = None
     L: object = None               # results, device-resident
     Sigma: object = None
     logdet: float = float("nan")
     info: tuple = (None, None)
     done: float = float("nan")     # completion time on the server's clock
-    nbytes: int = 0
+    nbytes: int = 0                # bytes charged to the budget while held
 
     @property
     def n(self) -> int:
@@ -48,21 +63,30 @@ class Job:
 
 
 def job_bytes(lay: st.Layout) -> int:
-    """Device bytes a job holds while it runs: L (factored in place over its
-    packed input), Sigma and its part of a batch workspace."""
-    return 2 * 8 * lay.total_doubles + max(lay.factor_workspace_bytes, lay.selinv_workspace_bytes) + 4096
+    """Device bytes a job holds from admission until its results are released:
+    L (factored in place over its packed input), Sigma, and its input in
+    canonical band form (dropped once packed, counted until release)."""
+    w = min(lay.bandwidth, max(lay.nb - 1, 0))
+    inp = 8 * ((w + 1) * lay.nb + lay.arrow * lay.nb + lay.arrow * lay.arrow)
+    return 2 * 8 * lay.total_doubles + inp
 
 
-def admit(queue: List[Job], room: int, max_batch: int) -> List[Job]:
+def admit(queue: List[Job], room: int, max_batch: int,
+          extra: Optional[Callable[[List[Job]], int]] = None) -> List[Job]:
     """Take the next batch off the head of the queue, in arrival order: jobs
-    join while they fit the free bytes `room` and the batch has fewer than
-    `max_batch` jobs; the first job that does not fit stops the batch (no job
-    overtakes an earlier one)."""
-    batch = []
-    while queue and len(batch) < max_batch and queue[0].nbytes <= room:
-        j = queue.pop(0)
-        batch.append(j)
-        room -= j.nbytes
+    join while the batch's bytes -- its jobs' `nbytes` plus `extra(batch)` (the
+    growth of the lane's workspace the batch would need) -- fit the free bytes
+    `room`, and the batch has fewer than `max_batch` jobs; the first job that
+    does not fit stops the batch (no job overtakes an earlier one)."""
+    batch: List[Job] = []
+    held = 0
+    while queue and len(batch) < max_batch:
+        cand = batch + [queue[0]]
+        need = held + queue[0].nbytes + (extra(cand) if extra is not None else 0)
+        if need > room:
+            break
+        held += queue[0].nbytes
+        batch.append(queue.pop(0))
     return batch
 
 
@@ -71,6 +95,7 @@ class _Lane:
     stream: object
     jobs: List[Job] = field(default_factory=list)
     ws: object = None
+    ws_bytes: int = 0
     ev_done: object = None
     logdet: object = None
     info: object = None
@@ -88,14 +113,26 @@ class Server:
         self.keep = keep_results
         self.on_done = on_done       # called with each finished job while its results are on the device
         self.lanes = [_Lane(torch.cuda.Stream()) for _ in range(lanes)]
-        self.in_use = 0
+        self.in_use = 0              # bytes held: admitted jobs until released, lane workspaces
+        self.peak = 0
         self.finished: List[Job] = []
+
+    def _ws_growth(self, lane: _Lane) -> Callable[[List[Job]], int]:
+        def growth(batch: List[Job]) -> int:
+            return max(0, st.batch_workspace_bytes([j.lay for j in batch]) - lane.ws_bytes)
+        return growth
+
+    def _charge(self, nbytes: int) -> None:
+        self.in_use += nbytes
+        self.peak = max(self.peak, self.in_use)
 
     def _launch(self, lane: _Lane, batch: List[Job], clock_ev, t0: float):
         import torch
         with torch.cuda.stream(lane.stream):
             As = []
             for j in batch:
+                if j.make is not None:
+                    j.ab, j.P, j.C = j.make()
                 As.append(st.pack(j.ab, j.P, j.C, j.lay, stream=lane.stream))
                 for x in (j.ab, j.P, j.C):       # inputs released once packed
                     if x is not None:
@@ -103,8 +140,11 @@ class Server:
                 j.ab = j.P = j.C = None
             lays = [j.lay for j in batch]
             need = st.batch_workspace_bytes(lays)
-            if lane.ws is None or lane.ws.numel() < need:
+            if need > lane.ws_bytes:
+                lane.ws = None
                 lane.ws = torch.empty(need, dtype=torch.uint8, device=As[0].device)
+                self._charge(need - lane.ws_bytes)
+                lane.ws_bytes = need
             Ls, ld, info = st.factor_batched(As, lays, outs=As, workspace=lane.ws, stream=lane.stream)
             Ss, info = st.selinv_batched(Ls, lays, workspace=lane.ws, info=info, stream=lane.stream)
             ev = torch.cuda.Event(enable_timing=True)
@@ -126,11 +166,30 @@ class Server:
             self.finished.append(j)
         lane.jobs, lane.ev_done = [], None
 
+    def _shrink_idle(self) -> bool:
+        """Give back the workspaces of idle lanes; True if any was held."""
+        freed = False
+        for lane in self.lanes:
+            if not lane.jobs and lane.ws_bytes:
+                lane.stream.synchronize()
+                lane.ws = None
+                self.in_use -= lane.ws_bytes
+                lane.ws_bytes = 0
+                freed = True
+        return freed
+
     def release(self, job: Job) -> None:
         """Drop a finished job's device results and give its bytes back to the budget."""
         if job.nbytes and job.L is not None:
             job.L = job.Sigma = None
             self.in_use -= job.nbytes
+
+    def close(self) -> None:
+        """Give back every lane workspace (after the last run)."""
+        for lane in self.lanes:
+            lane.stream.synchronize()
+            self.in_use -= lane.ws_bytes
+            lane.ws, lane.ws_bytes = None, 0
 
     def run(self, jobs: List[Job], clock: Callable[[], float] = time.perf_counter) -> List[Job]:
         """Serve `jobs` (sorted by arrival; arrival times on `clock`, in seconds
@@ -139,8 +198,9 @@ class Server:
         for j in jobs:
             j.lay = st.layout(j.n, j.w, j.a, self.tile)
             j.nbytes = job_bytes(j.lay)
-            if j.nbytes > self.budget:
-                raise ValueError(f"job {j.jid} needs {j.nbytes} bytes, over the budget of {self.budget}")
+            alone = j.nbytes + st.batch_workspace_bytes([j.lay])
+            if alone > self.budget:
+                raise ValueError(f"job {j.jid} needs {alone} bytes, over the budget of {self.budget}")
         clock_ev = torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         clock_ev.record()
@@ -161,13 +221,16 @@ class Server:
             for lane in self.lanes:
                 if lane.jobs or not queue:
                     continue
-                batch = admit(queue, self.budget - self.in_use, self.max_batch)
+                batch = admit(queue, self.budget - self.in_use, self.max_batch, self._ws_growth(lane))
                 if batch:
-                    self.in_use += sum(j.nbytes for j in batch)
+                    self._charge(sum(j.nbytes for j in batch))
                     self._launch(lane, batch, clock_ev, t0)
                     progressed = True
-            if queue and not any(l.jobs for l in self.lanes) and queue[0].nbytes > self.budget - self.in_use:
-                raise RuntimeError("the budget is held by results not released (Server.release)")
+            if queue and not any(l.jobs for l in self.lanes):
+                # nothing runs and the head does not fit: idle workspaces go back first
+                if not progressed and not self._shrink_idle():
+                    raise RuntimeError("the budget is held by results not released (Server.release)")
+                continue
             if not progressed:
                 time.sleep(2e-4)
         return self.finished
@@ -186,7 +249,10 @@ def serve_plain(jobs: List[Job], tile: int, clock: Callable[[], float] = time.pe
         while clock() - t_base < j.arrival:
             time.sleep(2e-4)
         j.lay = st.layout(j.n, j.w, j.a, tile)
+        if j.make is not None:
+            j.ab, j.P, j.C = j.make()
         A = st.pack(j.ab, j.P, j.C, j.lay)
+        j.ab = j.P = j.C = None
         L, ld, info = st.factor(A, j.lay, out=A)
         S, sinfo = st.selinv(L, j.lay)
         ev = torch.cuda.Event(enable_timing=True)
