@@ -26,7 +26,12 @@ PEAK_F64_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
 # WRITE_SIZE runs scaled by a copy of known size (profiles/k_factor_all_large_hbm_traffic.md),
 # valid only for the kernel sources they were taken with (sha256 prefix of csrc/*)
 # and the workload named.
-MEASURED_TRAFFIC = {("factor", "large"): {"bytes_per_launch": 13.240e9, "sources": "db321231634b1f5e"}}
+MEASURED_TRAFFIC = {("factor", "large"): {"bytes_per_launch": 13.283e9, "sources": "7840886ed5252816"}}
+# FP64 matrix-core counters of the same launch (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 flops and
+# SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE x SIMDs; profiles/mfma_f64_large_counters.md),
+# valid for the kernel sources they were taken with.
+MEASURED_MFMA = {("factor", "large"): {"mfma_flops_per_launch": 2.034e11, "mfma_busy": 0.066,
+                                        "sources": "7840886ed5252816"}}
 
 
 def sources_hash() -> str:
@@ -243,9 +248,26 @@ def main() -> int:
     dom = max((k for k in per_kind if k != "other"), key=lambda k: per_kind[k][0])
     dom_ms, dom_launches = per_kind[dom]
     achieved = kf[dom] * args.steps / (dom_ms / 1e3) / 1e12 if dom_ms > 0 else 0.0
+    src = sources_hash()
     mt = MEASURED_TRAFFIC.get((dom, args.workload))
-    traffic = mt["bytes_per_launch"] if mt and mt["sources"] == sources_hash() else None
+    traffic = mt["bytes_per_launch"] if mt and mt["sources"] == src else None
+    mm = MEASURED_MFMA.get((dom, args.workload))
+    mm = mm if mm and mm["sources"] == src else None
+    # the FP64 matrix-core rate this device sustains (pure-MFMA probe, best of 3)
+    peak_meas = None
+    try:
+        best = 0.0
+        for _ in range(3):
+            fl, ms = st.mfma_peak(4096)
+            best = max(best, fl / (ms / 1e3) / 1e12)
+        peak_meas = round(best, 2)
+    except Exception as e:   # measurement support only; the step above is the result
+        print(f"bench: matrix-core probe failed: {e}", file=sys.stderr, flush=True)
     roofline = {"bound": "mfma", "kernel": dom, "achieved": round(achieved, 3), "peak": PEAK_F64_TFLOPS,
+                "measured_peak": peak_meas,
+                "frac_of_measured_peak": round(achieved / peak_meas, 4) if peak_meas else None,
+                "mfma_counters": None if mm is None else {
+                    "mfma_flops_per_launch": mm["mfma_flops_per_launch"], "mfma_busy": mm["mfma_busy"]},
                 "unit": "TFLOP/s", "frac": round(achieved / PEAK_F64_TFLOPS, 4), "traffic": traffic,
                 "launches_per_step": dom_launches // max(args.steps, 1),
                 "avg_launch_us": round(dom_ms * 1e3 / max(dom_launches, 1), 2)}

@@ -74,8 +74,11 @@ typedef struct stiles_layout {
 } stiles_layout;
 
 /*
- * Fill *out with the tile layout of a matrix (host only, no GPU call).
- * Returns 0, or -i for an invalid argument i.
+ * Fill *out with the tile layout of a matrix (host only, no GPU call): this
+ * library's form of the compressed tile format that the method keeps the
+ * matrix in (selection step of Sec. III-B), for the arrowhead structure of
+ * Sec. II-III (band tiles within B of the diagonal, the arrow rows as a tile
+ * row of their own, the corner).  Returns 0, or -i for an invalid argument i.
  */
 int stiles_layout_init(int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile,
                        stiles_layout* out);
@@ -267,7 +270,23 @@ int stiles_trace_product(const double* Sigma, const double* B, int64_t n, int64_
 int stiles_timing_enable(int on);
 int stiles_timing_collect(double* ms, int64_t* launches);
 
-/* Static text for a return or info code. */
+/*
+ * Matrix-core throughput probe (measurement support, not part of the method):
+ * enqueues one launch of 2 workgroups per compute unit in which every
+ * wavefront issues `iters` x 8 independent FP64 16x16x4 matrix-core products,
+ * and sets *flops (host) to the floating-point operations it performs, so
+ * that flops / elapsed time is the FP64 matrix-core rate the device sustains.
+ *   sink   device, at least 512 doubles per compute unit (results are junk,
+ *          written only so the work is kept).
+ * Returns -1 (sink too small or NULL), -3 (iters < 1), -4 (flops NULL), or
+ * STILES_EHIP.
+ */
+int stiles_mfma_peak(double* sink, int64_t sink_doubles, int32_t iters, double* flops, void* stream);
+
+/* Static text for a return or info code.  A positive code k is the LAPACK
+ * potrf convention for the first non-positive pivot (the factor's diagonal
+ * tile kernel is the POTRF named in Sec. III-F); the negative codes are the
+ * argument and runtime errors listed above. */
 const char* stiles_strerror(int code);
 
 /* Library version, major*10000 + minor*100 + patch. */

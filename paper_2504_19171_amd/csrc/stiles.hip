@@ -1611,6 +1611,26 @@ __global__ __launch_bounds__(NT) void k_inv_compact(const double* D, int64_t ldd
 // Host side
 // ---------------------------------------------------------------------------
 
+// Pure matrix-core throughput: every wavefront runs 8 independent chains of
+// v_mfma_f64_16x16x4_f64 (2048 flops each), so the matrix pipe of its SIMD
+// never waits on a result.  sink keeps the compiler from dropping the work.
+#define PEAK_CHAINS 8
+__global__ __launch_bounds__(NT) void k_mfma_peak(double* sink, int iters) {
+    const int lane = threadIdx.x & 63;
+    const double a = 1.0 + 1e-3 * lane, b = 1.0 - 1e-3 * lane;
+    dbl4 acc[PEAK_CHAINS];
+#pragma unroll
+    for (int c = 0; c < PEAK_CHAINS; ++c) acc[c] = dbl4{0.0, 0.0, 0.0, (double)c};
+    for (int it = 0; it < iters; ++it) {
+#pragma unroll
+        for (int c = 0; c < PEAK_CHAINS; ++c) acc[c] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[c], 0, 0, 0);
+    }
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < PEAK_CHAINS; ++c) s += acc[c][0] + acc[c][1] + acc[c][2] + acc[c][3];
+    sink[blockIdx.x * (int64_t)NT + threadIdx.x] = s;
+}
+
 static inline hipStream_t S_(void* s) { return (hipStream_t)s; }
 
 #define HIPCHK(x)                              \
@@ -2060,6 +2080,19 @@ int stiles_gather(const double* Sigma, int64_t n, int64_t bandwidth, int64_t arr
     if (!out) return -8;
     LAUNCH(STILES_TK_OTHER, k_gather, dim3(grid_for(count)), dim3(NT), 0, S_(stream), Sigma, to_dev(lay), ij, count,
            out);
+    return 0;
+}
+
+int stiles_mfma_peak(double* sink, int64_t sink_doubles, int32_t iters, double* flops, void* stream) {
+    if (!flops) return -4;
+    if (iters < 1) return -3;
+    DevInfo di;
+    if (dev_info(&di)) return STILES_EHIP;
+    const int64_t blocks = 2 * (int64_t)di.cus;
+    if (!sink || sink_doubles < blocks * NT) return -1;
+    *flops = (double)blocks * (NT / 64) * (double)iters * PEAK_CHAINS * 2048.0;
+    hipLaunchKernelGGL(k_mfma_peak, dim3((unsigned)blocks), dim3(NT), 0, S_(stream), sink, (int)iters);
+    LAUNCHCHK();
     return 0;
 }
 

@@ -44,6 +44,7 @@ EXPORTED = (
     "stiles_inverse",
     "stiles_selinv_range",
     "stiles_gather",
+    "stiles_mfma_peak",
 )
 
 TIMING_KINDS = ("potrf", "trsm", "update", "phase1", "phase2", "factor", "other")
@@ -118,6 +119,8 @@ def load(path: Optional[str] = None):
     lib.stiles_trace_workspace_bytes.restype = _sz
     lib.stiles_trace_product.argtypes = [_vp, _vp, _i64, _i64, _i64, _i32, _vp, _vp, _sz, _vp]
     lib.stiles_trace_product.restype = ctypes.c_int
+    lib.stiles_mfma_peak.argtypes = [_vp, _i64, _i32, ctypes.POINTER(ctypes.c_double), _vp]
+    lib.stiles_mfma_peak.restype = ctypes.c_int
     lib.stiles_batch_workspace_bytes.argtypes = [ctypes.POINTER(_CBatchItem), _i32]
     lib.stiles_batch_workspace_bytes.restype = _sz
     lib.stiles_factor_batched.argtypes = [ctypes.POINTER(_CBatchItem), _i32, _vp, _sz, _vp]
@@ -253,6 +256,25 @@ def selinv(L, lay: Layout, out=None, workspace=None, stream=None):
         if rc != 0:
             raise StilesError(rc, "stiles_selinv")
         return S, info
+
+
+def mfma_peak(iters: int = 4096, stream=None) -> Tuple[float, float]:
+    """Launch the FP64 matrix-core throughput probe on the current device;
+    returns (flops, elapsed ms) measured with events on the launch's stream."""
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    with _on(stream):
+        n = 512 * torch.cuda.get_device_properties(torch.cuda.current_device()).multi_processor_count
+        sink = torch.empty(n, dtype=torch.float64, device="cuda")
+        flops = ctypes.c_double(0.0)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        rc = load().stiles_mfma_peak(sink.data_ptr(), n, int(iters), ctypes.byref(flops), _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_mfma_peak")
+        e1.record(s)
+        e1.synchronize()
+        return flops.value, e0.elapsed_time(e1)
 
 
 def timing_enable(on: bool = True) -> None:
