@@ -165,6 +165,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true",
                     help="large: skip the small, batched and served summaries of the default line")
     ap.add_argument("--extra-jobs", type=int, default=200, help="large: jobs of the served summary")
+    ap.add_argument("--fracs", default="0.5,0.8,1.5",
+                    help="served: arrival rates as fractions of the plain FIFO's capacity")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {args.gpus} is not supported "
@@ -385,6 +387,27 @@ def leg_batched(steps, warmup, tile=0, plain=True, device_inputs=False, log=prin
     step_ms = [ev[i].elapsed_time(ev[i + 1]) for i in range(steps)]
     ms_step = ev[0].elapsed_time(ev[-1]) / steps
 
+    # the same pass replayed from a HIP graph (the outputs land in the same
+    # buffers, so the comparison below checks the replayed results)
+    graph_ms = None
+    try:
+        g = autotune.capture_batched(buf)
+        g.replay()
+        torch.cuda.synchronize()
+        ge = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ge[0].record(stream)
+        for i in range(steps):
+            g.replay()
+        ge[1].record(stream)
+        torch.cuda.synchronize()
+        graph_ms = ge[0].elapsed_time(ge[1]) / steps
+        ok_graph = bool((buf["info"].cpu().numpy() == 0).all()) and bool(torch.equal(buf["ld"], ld))
+        del g
+    except Exception as e:   # reported, not hidden: the line then says the graph pass failed
+        log(f"bench: graph capture of the batched pass failed: {e}")
+        ok_graph = False
+    log(f"bench: batched pass from a HIP graph {graph_ms} ms (eager {ms_step:.3f} ms)")
+
     # every matrix: batched result == single-matrix result, bit for bit
     same = None if not plain else True
     for k, ((ab, P, C), lay) in enumerate(zip(mats, buf["lays"]) if plain else []):
@@ -394,7 +417,7 @@ def leg_batched(steps, warmup, tile=0, plain=True, device_inputs=False, log=prin
         same &= bool(torch.equal(L, buf["Ls"][k]) and torch.equal(S, buf["Ss"][k]))
         same &= float(ld1.item()) == float(ld[k].item())
         del A, L, S
-    ok = bool((info.cpu().numpy() == 0).all()) and bool(torch.isfinite(ld).all()) and same is not False
+    ok = bool((info.cpu().numpy() == 0).all()) and bool(torch.isfinite(ld).all()) and same is not False and ok_graph
     flop = sum(fl.factor_flops(n - a, w, a, tile) + fl.selinv_flops(n - a, w, a, tile) for (n, w, a) in nws)
     srt = sorted(step_ms)
     del buf, mats
@@ -406,6 +429,8 @@ def leg_batched(steps, warmup, tile=0, plain=True, device_inputs=False, log=prin
         "flops_per_pass": flop,
         "solves_per_s": round(len(shapes) * 1e3 / ms_step, 3),
         "pass_ms_p50": round(srt[len(srt) // 2], 4), "pass_ms_p99": round(srt[min(len(srt) - 1, int(0.99 * len(srt)))], 4),
+        "ms_per_pass_graph": None if graph_ms is None else round(graph_ms, 4),
+        "graph_speedup": None if graph_ms is None else round(ms_step / graph_ms, 4),
         "plain": None if plain_same is None else {
             "ms_same_tile": round(plain_same, 3), "ms_best_tile_each": round(plain_best, 3),
             "solves_per_s_same_tile": round(len(shapes) * 1e3 / plain_same, 3),
@@ -609,7 +634,7 @@ def leg_served(njobs, tile=0, budget_gb=64.0, lanes=3, max_batch=8, fracs=(0.5, 
 
 def main_served(args) -> int:
     r = leg_served(args.jobs, tile=args.tile, budget_gb=args.budget_gb, lanes=args.lanes,
-                   max_batch=args.max_batch, log=_log)
+                   max_batch=args.max_batch, fracs=tuple(float(x) for x in args.fracs.split(",")), log=_log)
     top = r["rates"]["0.8"]["served"]
     out = {
         "metric": METRIC,

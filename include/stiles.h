@@ -192,6 +192,27 @@ int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* w
                           size_t workspace_bytes, void* stream);
 
 /*
+ * The batched calls in two parts, for replay from a HIP graph (the batching
+ * of the method's calls, as above): stiles_batch_upload copies the tables of
+ * both calls for these items into their two areas of the workspace (from
+ * pageable host memory, stream-ordered, like the calls above; items need
+ * Sigma set); the _enqueue variants then only enqueue device work (kernels
+ * and, where A != L, device-to-device copies) that reads those tables and
+ * restarts every counter it uses, so a stream capture of them can be
+ * replayed any number of times.  Each _enqueue call must be given the same
+ * items, in the same order, as the upload that wrote the tables, and the
+ * workspace must not be used for another batch in between.  Per-kernel
+ * timing (stiles_timing_enable) must be off while a stream is captured.
+ * Arguments and return values as for the calls above.
+ */
+int stiles_batch_upload(const stiles_batch_item* items, int32_t count, void* workspace,
+                        size_t workspace_bytes, void* stream);
+int stiles_factor_batched_enqueue(const stiles_batch_item* items, int32_t count, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+int stiles_selinv_batched_enqueue(const stiles_batch_item* items, int32_t count, void* workspace,
+                                  size_t workspace_bytes, void* stream);
+
+/*
  * Selection (Sec. III-B, selection step and symbolic inversion).  A selected
  * (i, j) lies in tile column J (J = j / b in the band part, or the corner);
  * the recurrence for tile column J reads only tile columns to its right, so

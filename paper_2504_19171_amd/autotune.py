@@ -45,6 +45,39 @@ def run_batched(buf):
     return ld, info
 
 
+def capture_batched(buf):
+    """pack + batched factor + batched selinv of this batch captured in a HIP
+    graph (torch.cuda.CUDAGraph): the tables of the batched calls are copied
+    once (stiles_batch_upload) and the graph holds device work only, so
+    g.replay() repeats the whole pass.  buf gains the log det and info tensors
+    the graph writes ("ld", "info")."""
+    import torch
+    n = len(buf["lays"])
+    dev = buf["As"][0].device
+    buf["ld"] = torch.empty(n, dtype=torch.float64, device=dev)
+    buf["info"] = torch.zeros((n, 2), dtype=torch.int32, device=dev)
+    st.batch_upload(buf["lays"], buf["As"], buf["Ls"], buf["Ss"], buf["ld"], buf["info"], buf["ws"])
+
+    def body():
+        for (A, lay), (ab, P, C) in zip(zip(buf["As"], buf["lays"]), buf["mats"]):
+            st.pack(ab, P, C, lay, out=A)
+        st.factor_batched(buf["As"], buf["lays"], outs=buf["Ls"], workspace=buf["ws"], info=buf["info"],
+                          logdet=buf["ld"], enqueue_only=True)
+        st.selinv_batched(buf["Ls"], buf["lays"], outs=buf["Ss"], workspace=buf["ws"], info=buf["info"],
+                          As=buf["As"], logdet=buf["ld"], enqueue_only=True)
+
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        body()          # one eager pass on a side stream before the capture
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        body()
+    return g
+
+
 def time_batched(mats, shapes, tile, reps: int = 1) -> Tuple[float, dict]:
     """Milliseconds of one batched pass at this tile size (after one untimed pass)."""
     import torch

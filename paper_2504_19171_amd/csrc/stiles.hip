@@ -1782,7 +1782,8 @@ static size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 struct BPlan {
     std::vector<stiles_layout> lay;
     std::vector<size_t> off;   // workspace offset of each matrix
-    size_t table = 0;          // bytes of the table area
+    size_t table_f = 0;        // bytes of the factor's table area (at the start of the workspace)
+    size_t table = 0;          // bytes of both table areas (the selected inverse's follows the factor's)
     size_t total = 0;
     int64_t maxN = 0;
 };
@@ -1825,7 +1826,8 @@ static int batch_plan(const stiles_batch_item* items, int count, bool need_sigma
     }
     const size_t nseg = 6 * ((size_t)count + 1);
     const size_t nint = (size_t)count + 1 + (size_t)pl.maxN + (size_t)pl.maxN * (size_t)(tmax + 1) + (size_t)sumN;
-    pl.table = align256(sizeof(BInst) * (size_t)count) + align256(sizeof(BSeg) * nseg) + align256(sizeof(int) * nint);
+    pl.table_f = align256(sizeof(BInst) * (size_t)count) + align256(sizeof(BSeg) * nseg) + align256(sizeof(int) * nint);
+    pl.table = pl.table_f + align256(sizeof(BInst) * (size_t)count) + align256(sizeof(BSeg) * nseg);
     size_t o = pl.table;
     for (int k = 0; k < count; ++k) {
         pl.off[k] = o;
@@ -2188,8 +2190,13 @@ static int batch_upload(const std::vector<BInst>& bi, const std::vector<BSeg>& s
     return 0;
 }
 
-int stiles_factor_batched(const stiles_batch_item* items, int32_t count, void* workspace, size_t workspace_bytes,
-                          void* stream) {
+// What a batched call does: upload its tables (host -> workspace, a copy
+// from pageable memory staged before the call returns), enqueue its kernels
+// (device work only, reading the tables; what a HIP graph can capture), or both.
+#define BATCH_UPLOAD 1
+#define BATCH_LAUNCH 2
+static int factor_batched_impl(const stiles_batch_item* items, int32_t count, void* workspace,
+                               size_t workspace_bytes, void* stream, int mode) {
     if (!items) return -1;
     if (count < 1) return -2;
     BPlan pl;
@@ -2253,13 +2260,19 @@ int stiles_factor_batched(const stiles_batch_item* items, int32_t count, void* w
         q.order_at = ints.size();
         for (const auto& e : nt_k) ints.push_back(e.second);
     }
-    int rc = batch_upload(bi, segs, ints, ws, st);
-    if (rc) return rc;
+    int rc = 0;
+    if (mode & BATCH_UPLOAD) {
+        rc = batch_upload(bi, segs, ints, ws, st);
+        if (rc) return rc;
+    }
+    if (!(mode & BATCH_LAUNCH)) return 0;
     const BInst* dbi = (const BInst*)ws;
     const BSeg* dseg = (const BSeg*)(ws + seg0);
     int* dint = (int*)(ws + int0);
     const int64_t spin = spin_limit_ticks(di);
 
+    // the error word and the tile-column tickets start at zero on every run
+    LAUNCH(STILES_TK_OTHER, k_zero_ints, dim3(grid_for(1 + pl.maxN)), dim3(NT), 0, st, dint + err_at, 1 + pl.maxN);
     for (int k = 0; k < count; ++k) {
         if (bi[k].A == bi[k].Lm) continue;
         hipEvent_t tm = tm_begin(st);
@@ -2288,8 +2301,8 @@ int stiles_factor_batched(const stiles_batch_item* items, int32_t count, void* w
     return 0;
 }
 
-int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* workspace, size_t workspace_bytes,
-                          void* stream) {
+static int selinv_batched_impl(const stiles_batch_item* items, int32_t count, void* workspace,
+                               size_t workspace_bytes, void* stream, int mode) {
     if (!items) return -1;
     if (count < 1) return -2;
     BPlan pl;
@@ -2300,6 +2313,7 @@ int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* w
     DevInfo di;
     if (dev_info(&di)) return STILES_EHIP;
     char* ws = (char*)workspace;
+    char* tab = ws + pl.table_f;   // this call's table area
     std::vector<BInst> bi(count);
     int64_t sum_tasks = 0;
     for (int k = 0; k < count; ++k) {
@@ -2352,10 +2366,13 @@ int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* w
         }
     }
     close(p2);
-    int rc = batch_upload(bi, segs, std::vector<int>(), ws, st);
-    if (rc) return rc;
-    const BInst* dbi = (const BInst*)ws;
-    const BSeg* dseg = (const BSeg*)(ws + seg0);
+    if (mode & BATCH_UPLOAD) {
+        const int rc = batch_upload(bi, segs, std::vector<int>(), tab, st);
+        if (rc) return rc;
+    }
+    if (!(mode & BATCH_LAUNCH)) return 0;
+    const BInst* dbi = (const BInst*)tab;
+    const BSeg* dseg = (const BSeg*)(tab + seg0);
     const int64_t spin = spin_limit_ticks(di);
     auto args = [&](const Launch& l) { return BArgs{dbi, dseg + l.at, l.n, spin}; };
 
@@ -2367,6 +2384,33 @@ int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* w
     LAUNCH(STILES_TK_PHASE2, kb_phase2, dim3((unsigned)p2.grid), dim3(NT), 0, st, args(p2));
     LAUNCH(STILES_TK_OTHER, kb_selinv_final, dim3(count), dim3(64), 0, st, dbi);
     return 0;
+}
+
+int stiles_factor_batched(const stiles_batch_item* items, int32_t count, void* workspace, size_t workspace_bytes,
+                          void* stream) {
+    return factor_batched_impl(items, count, workspace, workspace_bytes, stream, BATCH_UPLOAD | BATCH_LAUNCH);
+}
+
+int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* workspace, size_t workspace_bytes,
+                          void* stream) {
+    return selinv_batched_impl(items, count, workspace, workspace_bytes, stream, BATCH_UPLOAD | BATCH_LAUNCH);
+}
+
+int stiles_batch_upload(const stiles_batch_item* items, int32_t count, void* workspace, size_t workspace_bytes,
+                        void* stream) {
+    const int rc = factor_batched_impl(items, count, workspace, workspace_bytes, stream, BATCH_UPLOAD);
+    if (rc) return rc;
+    return selinv_batched_impl(items, count, workspace, workspace_bytes, stream, BATCH_UPLOAD);
+}
+
+int stiles_factor_batched_enqueue(const stiles_batch_item* items, int32_t count, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+    return factor_batched_impl(items, count, workspace, workspace_bytes, stream, BATCH_LAUNCH);
+}
+
+int stiles_selinv_batched_enqueue(const stiles_batch_item* items, int32_t count, void* workspace,
+                                  size_t workspace_bytes, void* stream) {
+    return selinv_batched_impl(items, count, workspace, workspace_bytes, stream, BATCH_LAUNCH);
 }
 
 }  // extern "C"

@@ -45,6 +45,9 @@ EXPORTED = (
     "stiles_selinv_range",
     "stiles_gather",
     "stiles_mfma_peak",
+    "stiles_batch_upload",
+    "stiles_factor_batched_enqueue",
+    "stiles_selinv_batched_enqueue",
 )
 
 TIMING_KINDS = ("potrf", "trsm", "update", "phase1", "phase2", "factor", "other")
@@ -127,6 +130,9 @@ def load(path: Optional[str] = None):
     lib.stiles_factor_batched.restype = ctypes.c_int
     lib.stiles_selinv_batched.argtypes = [ctypes.POINTER(_CBatchItem), _i32, _vp, _sz, _vp]
     lib.stiles_selinv_batched.restype = ctypes.c_int
+    for name in ("stiles_batch_upload", "stiles_factor_batched_enqueue", "stiles_selinv_batched_enqueue"):
+        getattr(lib, name).argtypes = [ctypes.POINTER(_CBatchItem), _i32, _vp, _sz, _vp]
+        getattr(lib, name).restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -324,11 +330,13 @@ def batch_workspace_bytes(lays) -> int:
     return nbytes
 
 
-def factor_batched(As, lays, outs=None, workspace=None, info=None, stream=None):
+def factor_batched(As, lays, outs=None, workspace=None, info=None, stream=None, logdet=None, enqueue_only=False):
     """Cholesky factors of a batch; returns (Ls, logdet[count], info[count, 2]) on the device.
 
     ``outs[k]`` may be ``As[k]`` (in place).  ``info[:, 0]`` is each matrix's
     factor info (as :func:`factor`); column 1 is left for :func:`selinv_batched`.
+    enqueue_only: device work only, from the tables :func:`batch_upload` wrote
+    for the same matrices (``stiles_factor_batched_enqueue``; capturable).
     """
     with _on(stream):
         import torch
@@ -337,20 +345,37 @@ def factor_batched(As, lays, outs=None, workspace=None, info=None, stream=None):
         Ls = outs if outs is not None else [torch.empty_like(x) for x in As]
         ws = workspace if workspace is not None else torch.empty(batch_workspace_bytes(lays), dtype=torch.uint8,
                                                                  device=dev)
-        logdet = torch.empty(len(As), dtype=torch.float64, device=dev)
+        if logdet is None:
+            logdet = torch.empty(len(As), dtype=torch.float64, device=dev)
         if info is None:
             info = torch.zeros((len(As), 2), dtype=torch.int32, device=dev)
         items = _batch_items(lays, As=As, Ls=Ls, logdet=logdet, info=info)
-        rc = load().stiles_factor_batched(items, len(As), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+        fn = load().stiles_factor_batched_enqueue if enqueue_only else load().stiles_factor_batched
+        rc = fn(items, len(As), ws.data_ptr(), ws.numel(), _stream_handle(stream))
         if rc != 0:
             raise StilesError(rc, "stiles_factor_batched")
         return Ls, logdet, info
 
 
-def selinv_batched(Ls, lays, outs=None, workspace=None, info=None, stream=None):
+def batch_upload(lays, As, Ls, Ss, logdet, info, workspace, stream=None):
+    """Copy the tables of both batched calls for these matrices into the
+    workspace (``stiles_batch_upload``), ahead of enqueue-only calls."""
+    with _on(stream):
+        items = _batch_items(lays, As=As, Ls=Ls, Sigmas=Ss, logdet=logdet, info=info)
+        rc = load().stiles_batch_upload(items, len(lays), workspace.data_ptr(), workspace.numel(),
+                                        _stream_handle(stream))
+        if rc != 0:
+            raise StilesError(rc, "stiles_batch_upload")
+
+
+def selinv_batched(Ls, lays, outs=None, workspace=None, info=None, stream=None, As=None, logdet=None,
+                   enqueue_only=False):
     """Sigma on the tile pattern of every L of a batch; returns (Sigmas, info[count, 2]).
 
     ``info[:, 1]`` receives each matrix's selinv info (as :func:`selinv`).
+    enqueue_only: device work only (``stiles_selinv_batched_enqueue``), from
+    the tables :func:`batch_upload` wrote; the tensors must then be those given
+    to that upload.
     """
     with _on(stream):
         import torch
@@ -361,9 +386,10 @@ def selinv_batched(Ls, lays, outs=None, workspace=None, info=None, stream=None):
                                                                  device=dev)
         if info is None:
             info = torch.zeros((len(Ls), 2), dtype=torch.int32, device=dev)
-        dummy = torch.empty(len(Ls), dtype=torch.float64, device=dev)
-        items = _batch_items(lays, Ls=Ls, Sigmas=Ss, logdet=dummy, info=info)
-        rc = load().stiles_selinv_batched(items, len(Ls), ws.data_ptr(), ws.numel(), _stream_handle(stream))
+        dummy = logdet if logdet is not None else torch.empty(len(Ls), dtype=torch.float64, device=dev)
+        items = _batch_items(lays, As=As, Ls=Ls, Sigmas=Ss, logdet=dummy, info=info)
+        fn = load().stiles_selinv_batched_enqueue if enqueue_only else load().stiles_selinv_batched
+        rc = fn(items, len(Ls), ws.data_ptr(), ws.numel(), _stream_handle(stream))
         if rc != 0:
             raise StilesError(rc, "stiles_selinv_batched")
         return Ss, info

@@ -157,3 +157,45 @@ def test_batched_repeatable(mix_run, torch_cuda):
         torch.cuda.synchronize()
         for k in range(len(MIX)):
             assert torch.equal(Ls[k], r["Ls"][k]) and torch.equal(Ss[k], r["Ss"][k]), (rep, k)
+
+
+def test_graph_replay_equals_eager(torch_cuda):
+    """The batched pass (pack + factor + selinv) captured in a HIP graph from
+    the enqueue-only calls, replayed three times with other device work and
+    host synchronizations in between and the outputs filled with NaN before
+    each replay: every replay equals the eager batched pass bit for bit."""
+    torch = torch_cuda
+    from gpu_util import to_device
+    from paper_2504_19171_amd import autotune
+    from paper_2504_19171_amd import stiles as st
+    cases = [(2000, 32, 20), (777, 100, 33), (60, 10, 5), (900, 64, 300), (1300, 300, 0)]
+    mats, shapes = [], []
+    for k, (nb, w, a) in enumerate(cases):
+        M = inputs.arrowhead_spd(nb, w, a, seed=7000 + k)
+        ab, P, C = to_device(M, "cuda:0")
+        mats.append((ab, P, C))
+        shapes.append((M.n, w, a))
+    print(f"graph replay: {len(cases)} matrices, tile 64", flush=True)
+    ref = autotune.batch_buffers(mats, shapes, 64)
+    ref["mats"] = mats
+    ld0, info0 = autotune.run_batched(ref)
+    torch.cuda.synchronize()
+    assert (info0.cpu().numpy() == 0).all()
+    buf = autotune.batch_buffers(mats, shapes, 64)
+    buf["mats"] = mats
+    g = autotune.capture_batched(buf)
+    for rep in range(3):
+        for x in buf["Ls"] + buf["Ss"]:
+            x.fill_(float("nan"))
+        buf["ld"].fill_(float("nan"))
+        # other device work on the same buffers' stream between replays
+        other = st.factor(ref["As"][0], ref["lays"][0])[0]
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert (buf["info"].cpu().numpy() == 0).all(), rep
+        for k in range(len(cases)):
+            assert torch.equal(buf["Ls"][k], ref["Ls"][k]), (rep, k, "L")
+            assert torch.equal(buf["Ss"][k], ref["Ss"][k]), (rep, k, "Sigma")
+        assert torch.equal(buf["ld"], ld0), rep
+        del other
