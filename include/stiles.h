@@ -229,6 +229,21 @@ int stiles_selinv_batched_enqueue(const stiles_batch_item* items, int32_t count,
  *   pairs (device arrays: ij int64 [2 count], out double [count]); NaN for a
  *   pair outside the tile pattern of L or outside the matrix.
  */
+/*
+ * stiles_selection_closure: the symbolic step of a selection, on the host
+ *   (no device work).  For count pairs ij[2k], ij[2k+1] (host int64, either
+ *   order, 0 <= index < n): *inside (host int32) = 1 when every pair lies in
+ *   the tile pattern of L (a band pair whose tile row is at most B tiles below
+ *   its tile column, or any pair with an arrow index), else 0;
+ *   *first_column (host int64) = the leftmost tile column holding a selected
+ *   pair (N when every pair lies in the corner, or count == 0).  When *inside
+ *   is 1, stiles_selinv_range from *first_column followed by stiles_gather
+ *   yields every selected entry; otherwise some pair needs entries outside
+ *   the pattern (stiles_inverse).  Returns 0; -k for a bad argument k (-5
+ *   also for a pair outside the matrix); nothing is written on an error.
+ */
+int stiles_selection_closure(int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile, const int64_t* ij,
+                             int64_t count, int32_t* inside, int64_t* first_column);
 int stiles_selinv_range(const double* L, double* Sigma, int64_t n, int64_t bandwidth, int64_t arrow,
                         int32_t tile, int64_t first_column, int32_t* info, void* workspace,
                         size_t workspace_bytes, void* stream);

@@ -36,13 +36,26 @@ __host__ __device__ inline int imin_(int x, int y) { return x < y ? x : y; }
 __host__ __device__ inline int imax_(int x, int y) { return x > y ? x : y; }
 __host__ __device__ inline int64_t imax64(int64_t x, int64_t y) { return x > y ? x : y; }
 
+// Global (device) memory address space.  Every pointer the kernels read or
+// write through is global memory, but a pointer the compiler cannot trace
+// back to a kernel argument (one rebuilt from an integer, say) is generic,
+// and a generic access becomes a FLAT instruction.  FLAT loads and stores
+// count on the LDS counter as well as the memory one, so every wait for an
+// LDS access would also wait for every memory access in flight, and loads
+// issued ahead of their use would no longer overlap anything.  Casting to
+// this address space keeps such accesses GLOBAL instructions.
+#define GLOBAL_AS __attribute__((address_space(1)))
+
 // The same pointer in every lane, held in scalar registers: lets loads use a
 // scalar base plus a 32-bit per-lane offset instead of 64-bit addresses.
+// The pointer is rebuilt in the global address space (then converted back),
+// so accesses through it stay GLOBAL instructions.  p must point to device
+// memory.
 __device__ inline const double* uniform_ptr(const double* p) {
     const uint64_t v = (uint64_t)p;
     const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
     const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return (const double*)(((uint64_t)hi << 32) | lo);
+    return (const double*)(const GLOBAL_AS double*)(((uint64_t)hi << 32) | lo);
 }
 
 // base[idx] for a wave-uniform base and idx < 2^29: the byte offset is a
@@ -51,13 +64,13 @@ __device__ inline const double* uniform_ptr(const double* p) {
 __device__ inline double ld_s(const double* base, uint32_t idx) {
     uint32_t o = idx << 3;
     asm volatile("" : "+v"(o));   // keep the 64-bit address out of loop-invariant code motion
-    return *(const double*)((const char*)base + o);
+    return *(const GLOBAL_AS double*)((const char*)base + o);
 }
 
 __device__ inline void st_s(double* base, uint32_t idx, double v) {
     uint32_t o = idx << 3;
     asm volatile("" : "+v"(o));
-    *(double*)((char*)base + o) = v;
+    *(GLOBAL_AS double*)((char*)base + o) = v;
 }
 
 // base[idx] = v as a device-coherent store (see st_coh below), with the same
@@ -65,19 +78,34 @@ __device__ inline void st_s(double* base, uint32_t idx, double v) {
 __device__ inline void st_coh_s(double* base, uint32_t idx, double v) {
     uint32_t o = idx << 3;
     asm volatile("" : "+v"(o));
-    __hip_atomic_store((double*)((char*)base + o), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((GLOBAL_AS double*)((char*)base + o), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline double ld_coh_s(const double* base, uint32_t idx) {
     uint32_t o = idx << 3;
     asm volatile("" : "+v"(o));
-    return __hip_atomic_load((const double*)((const char*)base + o), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((const GLOBAL_AS double*)((const char*)base + o), __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Device-coherent load / store of one double (agent-scope relaxed atomics:
 // they bypass the non-coherent cache levels, see persist.hpp).
 __device__ inline double ld_coh(const double* p) {
-    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load((const GLOBAL_AS double*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 __device__ inline void st_coh(double* p, double v) {
-    __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store((GLOBAL_AS double*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Device-coherent int load / fetch-and-add (counters and flags handed between
+// workgroups), and the first error code of a kernel into *err (0 = none).
+__device__ inline int ld_coh_i(const int* p) {
+    return __hip_atomic_load((const GLOBAL_AS int*)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline int add_coh_i(int* p, int v) {
+    return __hip_atomic_fetch_add((GLOBAL_AS int*)p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ inline void set_error_once(int* err, int code) {
+    int zero = 0;
+    __hip_atomic_compare_exchange_strong((GLOBAL_AS int*)err, &zero, code, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                         __HIP_MEMORY_SCOPE_AGENT);
 }

@@ -42,11 +42,11 @@ struct Sched {
 __device__ inline int sched_next(const Sched& s, int ntasks, int* sh) {
     __syncthreads();
     if (threadIdx.x == 0) {
-        int t = -1;
-        if (__hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-            t = __hip_atomic_fetch_add(s.ticket, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (t >= ntasks) t = -1;
-        }
+        // both requests in flight at once: a ticket taken after an error is
+        // simply dropped
+        const int e = ld_coh_i(s.err);
+        int t = add_coh_i(s.ticket, 1);
+        if (e != 0 || t >= ntasks) t = -1;
         *sh = t;
     }
     __syncthreads();
@@ -60,18 +60,66 @@ __device__ inline int sched_next(const Sched& s, int ntasks, int* sh) {
 __device__ inline bool sched_wait(const Sched& s, int* flag, int target, int* sh) {
     if (threadIdx.x == 0) {
         int ok = 1;
-        if (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        if (ld_coh_i(flag) < target) {
             const int64_t t0 = wall_clock64();
-            while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (__hip_atomic_load(s.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+            while (ld_coh_i(flag) < target) {
+                if (ld_coh_i(s.err) != 0) { ok = 0; break; }
                 if (wall_clock64() - t0 > s.spin_limit) {
-                    int zero = 0;
-                    __hip_atomic_compare_exchange_strong(s.err, &zero, STILES_ETIMEOUT, __ATOMIC_RELAXED,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    set_error_once(s.err, STILES_ETIMEOUT);
                     ok = 0;
                     break;
                 }
                 __builtin_amdgcn_s_sleep(2);
+            }
+        }
+        *sh = ok;
+    }
+    __syncthreads();
+    const bool ok = __builtin_amdgcn_readfirstlane(*sh) != 0;
+    __syncthreads();   // every thread has read *sh before it can be reused
+    return ok;
+}
+
+// Wait until flag[i] >= target[i] for every i < n (n <= SCHED_MAX_DEPS), then
+// acquire for every thread.  Thread 0 reads all the counters at once; while
+// some are short it polls only the first of those (one hot counter per
+// waiting workgroup: the polls of hundreds of waiting workgroups share the
+// memory channels of a few counters).  Returns false if the kernel must stop.
+#define SCHED_MAX_DEPS 3
+struct SchedDeps {
+    int* flag[SCHED_MAX_DEPS];
+    int target[SCHED_MAX_DEPS];
+    int n;
+};
+__device__ inline void deps_add(SchedDeps& d, int* flag, int target) {
+    d.flag[d.n] = flag;
+    d.target[d.n] = target;
+    ++d.n;
+}
+__device__ inline bool sched_wait_deps(const Sched& s, const SchedDeps& d, int* sh) {
+    if (threadIdx.x == 0) {
+        int ok = 1;
+        int v[SCHED_MAX_DEPS];
+#pragma unroll
+        for (int i = 0; i < SCHED_MAX_DEPS; ++i) v[i] = i < d.n ? ld_coh_i(d.flag[i]) : 0;
+        int64_t t0 = -1;
+        unsigned polls = 0;
+#pragma unroll
+        for (int i = 0; i < SCHED_MAX_DEPS; ++i) {
+            if (i >= d.n || !ok) continue;
+            int x = v[i];
+            while (x < d.target[i]) {
+                if (t0 < 0) t0 = wall_clock64();
+                // the error word is one address for every workgroup: read it
+                // on every 16th poll only
+                if ((polls++ & 15) == 0 && ld_coh_i(s.err) != 0) { ok = 0; break; }
+                if (wall_clock64() - t0 > s.spin_limit) {
+                    set_error_once(s.err, STILES_ETIMEOUT);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(2);
+                x = ld_coh_i(d.flag[i]);
             }
         }
         *sh = ok;
@@ -87,8 +135,7 @@ __device__ inline bool sched_wait(const Sched& s, int* flag, int target, int* sh
 __device__ inline void sched_signal(const Sched& s, int* flag, int ticket) {
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
-    if (threadIdx.x == 0 && ticket != s.withhold)
-        __hip_atomic_fetch_add(flag, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0 && ticket != s.withhold) add_coh_i(flag, 1);
 }
 
 // Optional task tracing, compiled in with -DSTILES_TASK_TRACE (diagnostics

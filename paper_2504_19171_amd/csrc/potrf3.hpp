@@ -540,10 +540,10 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
         // D, Y of p+1; panel p+1 in the pool; Dn; and the stores of panel p
         // complete, so it is announced.
         p3_bar_all();
-        if (threadIdx.x == 0 && fpo) __hip_atomic_fetch_add(fpo, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (threadIdx.x == 0 && fpo) add_coh_i(fpo, 1);
     }
     p3_bar_all();   // the last panel's stores complete
-    if (threadIdx.x == 0 && fpo) __hip_atomic_fetch_add(fpo, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (threadIdx.x == 0 && fpo) add_coh_i(fpo, 1);
     // log det: 2 log L_jj in parallel, then a fixed-order compensated sum
     // (lane l of wavefront 0 sums entries l, l+64, ..., then the lanes are
     // joined pairwise by a butterfly)

@@ -207,8 +207,11 @@ __global__ __launch_bounds__(NT) void k_zero_unused(double* T, Lay L) { zero_unu
 // POTRF of one m x m diagonal block (m <= 256), optional TRTRI of the result
 // into X, log det partial into ldp[0..1], first failing column into *info
 // (atomicMin of the 1-based global column col_base + c + 1).
-__device__ inline void potrf_body(double* M, int64_t ld, int m, double* X, int64_t ldx, double* ldp, int* info,
+__device__ __forceinline__ void potrf_body(double* M, int64_t ld, int m, double* X, int64_t ldx, double* ldp, int* info,
                                   int64_t col_base, double* smem) {
+    // device memory (a batched caller reads these pointers from its table)
+    M = (double*)(GLOBAL_AS double*)M;
+    if (X) X = (double*)(GLOBAL_AS double*)X;
     int fail;
     double s, c;
     potrf_tile(M, ld, m, smem, &fail, &s, &c);
@@ -501,12 +504,10 @@ __device__ inline bool col_wait(const Sched& sc, const int* flag, int n, int tar
         int ok = 1;
         const int64_t t0 = wall_clock64();
         for (int k = 0; k < n && ok; ++k) {
-            while (__hip_atomic_load(flag + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-                if (__hip_atomic_load(sc.err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) { ok = 0; break; }
+            while (ld_coh_i(flag + k) < target) {
+                if (ld_coh_i(sc.err) != 0) { ok = 0; break; }
                 if (wall_clock64() - t0 > sc.spin_limit) {
-                    int zero = 0;
-                    __hip_atomic_compare_exchange_strong(sc.err, &zero, STILES_ETIMEOUT, __ATOMIC_RELAXED,
-                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                    set_error_once(sc.err, STILES_ETIMEOUT);
                     ok = 0;
                     break;
                 }
@@ -904,9 +905,12 @@ struct P2 {
     double* S;
     const double* W;
     Lay L;
-    int* group_off;  // [N+1]: first ticket of group J = N-1-q at group_off[q]
     int* cnt;        // [P2_KINDS * N] finished tasks per kind and tile column
     int ntasks;
+    // groups are taken in the order G = N-1-q, q = 0, 1, ...; from q = q0 on,
+    // every group but the last (G = 0) holds g_tasks tasks, and group q0
+    // starts at ticket off_q0, so a ticket's group is found in closed form
+    int q0, off_q0, g_tasks;
 };
 
 struct P2Counts {
@@ -956,12 +960,6 @@ __device__ inline void p2_setup_body(const P2& p, int* ticket, int* err) {
     const Lay& L = p.L;
     for (int64_t i = threadIdx.x; i < P2_KINDS * L.nt; i += blockDim.x) p.cnt[i] = 0;
     if (threadIdx.x == 0) {
-        int acc = 0;
-        for (int64_t q = 0; q < L.nt; ++q) {
-            p.group_off[q] = acc;
-            acc += p2_group_tasks(L, L.nt - 1 - q);
-        }
-        p.group_off[L.nt] = acc;
         *ticket = 0;
         *err = 0;
     }
@@ -995,25 +993,28 @@ __device__ inline void p2_far_row(const Lay& L, int s, int rbg, int rb, int& d, 
     else { d = ARW; rbl = rbg - far * per; }
 }
 
-// Wait until every task of the given kind and tile column has finished.
-__device__ inline bool p2_wait_all(const P2& p, const Sched& sc, int kind, int64_t J, int* sh) {
-    return sched_wait(sc, &p.cnt[kind * p.L.nt + J], p2_counts(p.L, J).n[kind], sh);
+// Every task of the given kind and tile column finished (nothing to wait for
+// past the last column).
+__device__ inline void p2_dep_all(const P2& p, SchedDeps& d, int kind, int64_t J) {
+    if (J < p.L.nt) deps_add(d, &p.cnt[kind * p.L.nt + J], p2_counts(p.L, J).n[kind]);
 }
 // done(J): all of column J final.
-__device__ inline bool p2_wait_done(const P2& p, const Sched& sc, int64_t J, int* sh) {
-    if (J >= p.L.nt) return true;
-    return p2_wait_all(p, sc, p.L.s(J) >= 1 ? P2_DB : P2_DA, J, sh);
+__device__ inline void p2_dep_done(const P2& p, SchedDeps& d, int64_t J) {
+    if (J < p.L.nt) p2_dep_all(p, d, p.L.s(J) >= 1 ? P2_DB : P2_DA, J);
 }
 // far(J): the far rows of column J final.
-__device__ inline bool p2_wait_far(const P2& p, const Sched& sc, int64_t J, int* sh) {
-    if (J >= p.L.nt) return true;
-    return p2_wait_all(p, sc, p.L.s(J) >= 1 ? P2_L : P2_EA, J, sh);
+__device__ inline void p2_dep_far(const P2& p, SchedDeps& d, int64_t J) {
+    if (J < p.L.nt) p2_dep_all(p, d, p.L.s(J) >= 1 ? P2_L : P2_EA, J);
 }
 // offdiag(J): every off-diagonal tile of column J final.
-__device__ inline bool p2_wait_offdiag(const P2& p, const Sched& sc, int64_t J, int* sh) {
-    if (J >= p.L.nt) return true;
-    if (p.L.s(J) >= 1) return p2_wait_all(p, sc, P2_L, J, sh) && p2_wait_all(p, sc, P2_L1, J, sh);
-    return p2_wait_all(p, sc, P2_EA, J, sh);
+__device__ inline void p2_dep_offdiag(const P2& p, SchedDeps& d, int64_t J) {
+    if (J >= p.L.nt) return;
+    if (p.L.s(J) >= 1) {
+        p2_dep_all(p, d, P2_L, J);
+        p2_dep_all(p, d, P2_L1, J);
+    } else {
+        p2_dep_all(p, d, P2_EA, J);
+    }
 }
 
 #define P2_SMEM_DOUBLES (WS_SMEM_DOUBLES + 32 * WR_LD)
@@ -1123,13 +1124,26 @@ __device__ inline void p2_run(const P2& p, const Sched& sc, double* smem, int* s
         const int t = sched_next(sc, p.ntasks, &sh[0]);
         if (t < 0) break;
         TRACE(t, 0, wall_clock64());
-        int lo = 0, hi = (int)N;
-        while (hi - lo > 1) {
-            const int mid = (lo + hi) >> 1;
-            if (p.group_off[mid] <= t) lo = mid; else hi = mid;
+        // the group of ticket t: in closed form past group q0, else by
+        // walking the first q0 groups (arithmetic only, no memory reads)
+        int64_t q;
+        int base;
+        if (t >= p.off_q0) {
+            q = p.q0 + (t - p.off_q0) / p.g_tasks;
+            if (q > N - 1) q = N - 1;
+            base = p.off_q0 + (int)(q - p.q0) * p.g_tasks;
+        } else {
+            q = 0;
+            base = 0;
+            for (;;) {
+                const int n = p2_group_tasks(L, N - 1 - q);
+                if (t < base + n) break;
+                base += n;
+                ++q;
+            }
         }
-        const int64_t G = N - 1 - lo;       // group
-        int u = t - p.group_off[lo];
+        const int64_t G = N - 1 - q;       // group
+        int u = t - base;
         // decode (kind, J, index) inside group G
         int kind = -1;
         int64_t J = G;
@@ -1148,26 +1162,21 @@ __device__ inline void p2_run(const P2& p, const Sched& sc, double* smem, int* s
         }
         int* my = &p.cnt[kind * N + J];
 
-        // dependencies
-        bool ok = true;
+        // dependencies, all polled together
+        SchedDeps dp;
+        dp.n = 0;
         const bool two = L.s(J) >= 2;
         switch (kind) {
-            case P2_EA: ok = p2_wait_offdiag(p, sc, J + 2, &sh[1]); break;
-            case P2_EB: ok = p2_wait_done(p, sc, J + 2, &sh[1]) && p2_wait_all(p, sc, P2_EA, J, &sh[1]); break;
-            case P2_E1A: ok = p2_wait_far(p, sc, J + 1, &sh[1]); break;
-            case P2_E1B:
-                ok = p2_wait_all(p, sc, P2_L1, J + 1, &sh[1]) && p2_wait_all(p, sc, P2_E1A, J, &sh[1]);
-                break;
-            case P2_L:
-                ok = p2_wait_offdiag(p, sc, J + 1, &sh[1]) && p2_wait_all(p, sc, two ? P2_EB : P2_EA, J, &sh[1]);
-                break;
-            case P2_L1:
-                ok = p2_wait_done(p, sc, J + 1, &sh[1]) && p2_wait_all(p, sc, two ? P2_E1B : P2_E1A, J, &sh[1]);
-                break;
-            case P2_DA: ok = p2_wait_far(p, sc, J, &sh[1]); break;
-            default: ok = p2_wait_all(p, sc, P2_DA, J, &sh[1]) && p2_wait_all(p, sc, P2_L1, J, &sh[1]);
+            case P2_EA: p2_dep_offdiag(p, dp, J + 2); break;
+            case P2_EB: p2_dep_done(p, dp, J + 2); p2_dep_all(p, dp, P2_EA, J); break;
+            case P2_E1A: p2_dep_far(p, dp, J + 1); break;
+            case P2_E1B: p2_dep_all(p, dp, P2_L1, J + 1); p2_dep_all(p, dp, P2_E1A, J); break;
+            case P2_L: p2_dep_offdiag(p, dp, J + 1); p2_dep_all(p, dp, two ? P2_EB : P2_EA, J); break;
+            case P2_L1: p2_dep_done(p, dp, J + 1); p2_dep_all(p, dp, two ? P2_E1B : P2_E1A, J); break;
+            case P2_DA: p2_dep_far(p, dp, J); break;
+            default: p2_dep_all(p, dp, P2_DA, J); p2_dep_all(p, dp, P2_L1, J);
         }
-        if (!ok) break;
+        if (!sched_wait_deps(sc, dp, &sh[1])) break;
         TRACE(t, 1, wall_clock64());
 
         p2_task_small(p, kind, J, u, L.s(J) == 0, smem, red, t);
@@ -1229,7 +1238,7 @@ struct SelinvWs {
     int* ticket;    // Phase 2 ticket counter
     int* err;       // Phase 2 scheduler error word
     double* W;      // Phase 1 tiles (tile layout)
-    int* flags;     // Phase 2 group offsets and ready counters
+    int* flags;     // Phase 2 ready counters
 };
 __host__ __device__ inline SelinvWs selinv_ws(const Lay& L, char* ws) {
     SelinvWs v;
@@ -1246,9 +1255,14 @@ __host__ __device__ inline P2 make_p2(double* S, const SelinvWs& v, const Lay& L
     p.S = S;
     p.W = v.W;
     p.L = L;
-    p.group_off = v.flags;
-    p.cnt = v.flags + L.nt + 1;
+    p.cnt = v.flags;
     p.ntasks = ntasks;
+    const int64_t N = L.nt;
+    const int64_t qr = L.bt > 1 ? L.bt : 1;
+    p.q0 = (int)(N - 1 < qr ? N - 1 : qr);
+    p.off_q0 = 0;
+    for (int q = 0; q < p.q0; ++q) p.off_q0 += p2_group_tasks(L, N - 1 - q);
+    p.g_tasks = p.q0 < N - 1 ? p2_group_tasks(L, N - 1 - p.q0) : 1;
     return p;
 }
 
@@ -1798,9 +1812,9 @@ static size_t fws_bytes(const stiles_layout& l) {
 }
 // selinv workspace (SelinvWs): head (info, ticket, error words), the Phase 1
 // tiles (inverted diagonal tiles, Lhat, corner inverse) in the tile layout,
-// then the Phase 2 group offsets (N + 1) and ready counters (P2_KINDS N).
+// then the Phase 2 ready counters (P2_KINDS N).
 static size_t sws_bytes(const stiles_layout& l) {
-    return WS_HEAD + sizeof(double) * (size_t)l.total_doubles + sizeof(int) * (size_t)((1 + P2_KINDS) * l.nt + 1);
+    return WS_HEAD + sizeof(double) * (size_t)l.total_doubles + sizeof(int) * (size_t)(P2_KINDS * l.nt);
 }
 static int batch_plan(const stiles_batch_item* items, int count, bool need_sigma, BPlan& pl) {
     pl.lay.resize(count);
@@ -2082,6 +2096,33 @@ int stiles_gather(const double* Sigma, int64_t n, int64_t bandwidth, int64_t arr
     if (!out) return -8;
     LAUNCH(STILES_TK_OTHER, k_gather, dim3(grid_for(count)), dim3(NT), 0, S_(stream), Sigma, to_dev(lay), ij, count,
            out);
+    return 0;
+}
+
+int stiles_selection_closure(int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile, const int64_t* ij,
+                             int64_t count, int32_t* inside, int64_t* first_column) {
+    stiles_layout lay;
+    int rc = make_layout(n, bandwidth, arrow, tile, &lay);
+    if (rc) return rc;
+    if (count < 0) return -6;
+    if (count > 0 && !ij) return -5;
+    if (!inside) return -7;
+    if (!first_column) return -8;
+    const int64_t b = lay.tile, nb = lay.nb;
+    int32_t in = 1;
+    int64_t first = lay.nt;
+    for (int64_t k = 0; k < count; ++k) {
+        const int64_t i = ij[2 * k], j = ij[2 * k + 1];
+        const int64_t hi = i > j ? i : j, lo = i > j ? j : i;
+        if (lo < 0 || hi >= n) return -5;
+        // a band entry lies in L's tile pattern when its tile row is within
+        // B tiles of its tile column; arrow rows and the corner always do
+        if (hi < nb && hi / b - lo / b > lay.bt) in = 0;
+        const int64_t col = lo < nb ? lo / b : lay.nt;
+        if (col < first) first = col;
+    }
+    *inside = in;
+    *first_column = first;
     return 0;
 }
 

@@ -36,7 +36,7 @@ __host__ __device__ inline int potrf_smem_doubles(int m) { return 16 * TO_LDD + 
 // On return (all threads): *fail = first local column whose pivot was not
 // positive (or NaN), -1 if none; ld_sum + ld_comp = sum of 2 log(L_jj)
 // (Neumaier-compensated), valid in thread 0.
-__device__ inline void potrf_tile(double* M, int64_t ld, int m, double* smem, int* fail,
+__device__ __forceinline__ void potrf_tile(double* M, int64_t ld, int m, double* smem, int* fail,
                                   double* ld_sum, double* ld_comp) {
     double* sD = smem;                 // 16 x 17
     double* sR = smem + 16 * TO_LDD;   // 16 reciprocals of the pivots
@@ -158,7 +158,7 @@ __device__ inline void potrf_tile(double* M, int64_t ld, int m, double* smem, in
 // diagonals d = 1, 2, ... follow from X_IJ = -X_II sum_{K=J}^{I-1} L_IK X_KJ,
 // every block of one diagonal in parallel.  Returns 1 in *bad (all threads) if
 // a diagonal entry of L is not positive or is NaN.
-__device__ inline void trtri_tile(const double* L, int64_t ldl, double* X, int64_t ldx, int m,
+__device__ __forceinline__ void trtri_tile(const double* L, int64_t ldl, double* X, int64_t ldx, int m,
                                   double* smem, int* bad) {
     __shared__ int s_bad;
     const int t = threadIdx.x;

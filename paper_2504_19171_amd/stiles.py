@@ -26,6 +26,7 @@ STILES_EBADL = -102
 
 EXPORTED = (
     "stiles_layout_init",
+    "stiles_selection_closure",
     "stiles_pack",
     "stiles_factor_workspace_bytes",
     "stiles_selinv_workspace_bytes",
@@ -133,6 +134,9 @@ def load(path: Optional[str] = None):
     for name in ("stiles_batch_upload", "stiles_factor_batched_enqueue", "stiles_selinv_batched_enqueue"):
         getattr(lib, name).argtypes = [ctypes.POINTER(_CBatchItem), _i32, _vp, _sz, _vp]
         getattr(lib, name).restype = ctypes.c_int
+    lib.stiles_selection_closure.argtypes = [_i64, _i64, _i64, _i32, _vp, _i64, ctypes.POINTER(_i32),
+                                             ctypes.POINTER(_i64)]
+    lib.stiles_selection_closure.restype = ctypes.c_int
     if path is None:
         _lib = lib
     return lib
@@ -472,23 +476,21 @@ def gather(Sigma, lay: Layout, ij, out=None, stream=None):
 
 
 def selection_closure(lay: Layout, pairs):
-    """Host side of a selection (Sec. III-B): for pairs (i, j) -> (whether every
-    pair lies in the tile pattern of L, the first tile column of the closure).
-    In the pattern, the closure runs from the leftmost selected tile column to
-    the last (the corner alone is column N)."""
+    """Symbolic step of a selection (Sec. III-B) through stiles_selection_closure:
+    for pairs (i, j) -> (whether every pair lies in the tile pattern of L, the
+    first tile column of the closure; N when only the corner is selected)."""
     import numpy as np
-    p = np.asarray(pairs, dtype=np.int64).reshape(-1, 2)
-    hi = np.maximum(p[:, 0], p[:, 1])
-    lo = np.minimum(p[:, 0], p[:, 1])
-    if p.size and (lo.min() < 0 or hi.max() >= lay.n):
+    p = np.ascontiguousarray(np.asarray(pairs, dtype=np.int64).reshape(-1, 2))
+    inside = _i32(0)
+    first = _i64(0)
+    rc = load().stiles_selection_closure(lay.n, lay.bandwidth, lay.arrow, lay.tile,
+                                         p.ctypes.data if len(p) else None, len(p),
+                                         ctypes.byref(inside), ctypes.byref(first))
+    if rc == -5:
         raise ValueError("pair outside the matrix")
-    b, nb = lay.tile, lay.nb
-    band = hi < nb
-    inside = np.ones(len(p), dtype=bool)
-    inside[band] = (hi[band] // b - lo[band] // b) <= lay.bt
-    col = np.where(lo < nb, lo // b, lay.nt)
-    first = int(col.min()) if len(p) else lay.nt
-    return bool(inside.all()), first
+    if rc != 0:
+        raise StilesError(rc, "stiles_selection_closure")
+    return bool(inside.value), int(first.value)
 
 
 def select(L, lay: Layout, pairs, stream=None):

@@ -165,6 +165,41 @@ def test_selection_closure():
         st.selection_closure(lay, [(1020, 3)])
 
 
+def test_selection_closure_c_entry_point():
+    """The symbolic step runs behind the C ABI: empty selections, errors leave
+    the outputs untouched, and the leftmost selected tile column wins."""
+    import ctypes
+    lib = st.load()
+    inside, first = ctypes.c_int32(-9), ctypes.c_int64(-9)
+    assert lib.stiles_selection_closure(1020, 100, 20, 64, None, 0, ctypes.byref(inside), ctypes.byref(first)) == 0
+    assert (inside.value, first.value) == (1, 16)
+    ij = np.array([[1019, 0]], dtype=np.int64)                 # arrow row, tile column 0
+    assert lib.stiles_selection_closure(1020, 100, 20, 64, ij.ctypes.data, 1, ctypes.byref(inside),
+                                        ctypes.byref(first)) == 0
+    assert (inside.value, first.value) == (1, 0)
+    inside.value, first.value = -9, -9
+    bad = np.array([[3, -1]], dtype=np.int64)
+    assert lib.stiles_selection_closure(1020, 100, 20, 64, bad.ctypes.data, 1, ctypes.byref(inside),
+                                        ctypes.byref(first)) == -5
+    assert (inside.value, first.value) == (-9, -9)
+    assert lib.stiles_selection_closure(1020, 100, 20, 64, None, 1, ctypes.byref(inside), ctypes.byref(first)) == -5
+    assert lib.stiles_selection_closure(1020, 100, 20, 64, ij.ctypes.data, -1, ctypes.byref(inside),
+                                        ctypes.byref(first)) == -6
+    assert lib.stiles_selection_closure(1020, 100, 20, 64, ij.ctypes.data, 1, None, ctypes.byref(first)) == -7
+    assert lib.stiles_selection_closure(1020, 100, 20, 64, ij.ctypes.data, 1, ctypes.byref(inside), None) == -8
+    assert lib.stiles_selection_closure(1020, 100, 20, 60, ij.ctypes.data, 1, ctypes.byref(inside),
+                                        ctypes.byref(first)) == -4
+    # every pair of a small matrix: in the pattern exactly when its tile row is
+    # at most B tiles below its tile column or it touches the arrow
+    lay = st.layout(300, 70, 12, 64)                          # nb = 288, N = 5, B = 2
+    i, j = np.meshgrid(np.arange(300), np.arange(300), indexing="ij")
+    for a, c in zip(i.ravel()[::7], j.ravel()[::7]):
+        got = st.selection_closure(lay, [(a, c)])
+        hi, lo = max(a, c), min(a, c)
+        assert got[0] == (hi >= 288 or hi // 64 - lo // 64 <= 2)
+        assert got[1] == (lo // 64 if lo < 288 else 5)
+
+
 def test_selection_entry_points_reject_bad_arguments_before_any_gpu_call():
     lib = st.load()
     lay = st.layout(100, 4, 3, 64)
