@@ -10,8 +10,11 @@
 #include "common.hpp"
 
 // One contiguous piece of the reduction dimension.
-//   A(i, k) = ta ? a[k + i*lda] : a[i + k*lda]     i < 32 (rows >= avalid read as 0)
+//   A(i, k) = ta ? a[k + i*lda] : a[i + k*lda]     i < 32
 //   B(k, j) = tb ? b[j + k*ldb] : b[k + j*ldb]     j < 32
+//   avalid: rows of A that exist (even, and 32 when ta == 1).  Rows past it
+//     are filled with copies of existing rows, so the output rows >= avalid
+//     are meaningless and the caller discards them.
 //   ca / cb: read A / B with device-coherent loads (data written by other
 //   workgroups of the same kernel)
 struct Seg {
@@ -32,74 +35,90 @@ __device__ inline Seg mkseg(const double* a, int64_t lda, int ta, const double* 
     return s;
 }
 
-// Per-wavefront LDS staging: each wavefront fetches 16-deep chunks of its own
-// A (32 x 16) and B (16 x 32) with loads that run along the contiguous
-// dimension of each operand (coalesced whatever the orientation), writes them
-// to its private LDS area as [k][i] / [k][j], and feeds the MFMAs from there.
-#define WS_LD 33
-#define WS_WAVE_DOUBLES (2 * 16 * WS_LD)
+// Per-wavefront LDS staging with direct loads: a 16-deep chunk of A (32 x 16)
+// and of B (16 x 32) goes from memory straight into the wavefront's private
+// LDS area (global_load_lds_dwordx4: lane l's 16 bytes land at 16*l from the
+// instruction's base, 1 KB per instruction, 4 instructions per operand), two
+// chunks in flight in two buffers.  No registers hold data in flight and
+// nothing is copied into LDS by the wavefront itself.  Each lane fetches two
+// consecutive doubles along the contiguous dimension of its operand:
+//   contiguous along x (A with ta == 0, B with tb == 1): element (x, k) at
+//     [k*32 + x];
+//   contiguous along k: element (x, k) at [x*16 + 2*((k/2) ^ (x%8)) + k%2]
+//     (the pairs of a row permuted by the row index, so that the 16 rows a
+//     matrix-core operand read touches fall in different LDS banks).
+#define WS_CHUNK_DOUBLES 1024                        // A (512) + B (512)
+#define WS_WAVE_DOUBLES (2 * WS_CHUNK_DOUBLES)       // two buffers
 #define WS_SMEM_DOUBLES (4 * WS_WAVE_DOUBLES)
 
-// Order the LDS accesses of one wavefront (its lanes run in lockstep; this
-// waits for outstanding LDS operations and stops compiler reordering).
-__device__ inline void wave_lds_sync() {
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
+typedef __attribute__((address_space(3))) void lds_void_t;
 
-// 8 doubles of a 16-deep chunk of operand (x = output index, k = reduction).
+// Issue the loads of one 32 x 16 operand chunk (x = output index, k =
+// reduction index, k0 its first k) into dst (512 doubles of LDS).
 //   contig_x: element (x, k) at p[x + k*ld], else at p[k + x*ld].
-__device__ inline void ws_fetch(const double* p, int64_t ld, int contig_x, int valid, int k0, int coh,
-                                double r[8]) {
-    // offsets stay inside one operand tile (< 2^31 doubles)
+// COH: device-coherent loads.  Offsets stay inside one operand tile.
+template <int COH>
+__device__ inline void wl_fetch(const double* p, int64_t ld, int contig_x, int valid, int k0, double* dst) {
     const double* b = uniform_ptr(p);
     const int l = threadIdx.x & 63;
     const int ldi = (int)ld;
-    int o, st;
-    bool ok[8];
     if (contig_x) {
-        const int x = l & 31;
-        o = x + (k0 + (l >> 5)) * ldi;
-        st = 2 * ldi;
+        // instruction q: k = k0 + 4q + l/16, rows 2*(l%16), +1 (a pair past
+        // `valid` reads the last existing pair)
+        const int x2 = imin_(2 * (l & 15), valid - 2);
+        const double* g = b + x2 + (int64_t)(k0 + (l >> 4)) * ldi;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ok[q] = x < valid;
+        for (int q = 0; q < 4; ++q)
+            __builtin_amdgcn_global_load_lds((const void*)(g + (int64_t)(4 * q) * ldi),
+                                             (lds_void_t*)(dst + 128 * q), 16, 0, COH ? 16 : 0);
     } else {
-        const int x0 = l >> 4;
-        o = (k0 + (l & 15)) + x0 * ldi;
-        st = 4 * ldi;
+        // instruction q: row x = 8q + l/8, pair c = (l%8) ^ (l/8) of k
+        const int xl = l >> 3, c = (l & 7) ^ xl;
+        const double* g = b + (k0 + 2 * c) + (int64_t)xl * ldi;
 #pragma unroll
-        for (int q = 0; q < 8; ++q) ok[q] = x0 + 4 * q < valid;
-    }
-    if (coh) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) r[q] = ok[q] ? ld_coh(b + o + q * st) : 0.0;
-    } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) r[q] = ok[q] ? b[o + q * st] : 0.0;
+        for (int q = 0; q < 4; ++q)
+            __builtin_amdgcn_global_load_lds((const void*)(g + (int64_t)(8 * q) * ldi),
+                                             (lds_void_t*)(dst + 128 * q), 16, 0, COH ? 16 : 0);
     }
 }
 
-__device__ inline void ws_stash(double* s, int contig_x, const double r[8]) {
-    const int l = threadIdx.x & 63;
-    if (contig_x) {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s[((l >> 5) + 2 * q) * WS_LD + (l & 31)] = r[q];
-    } else {
-#pragma unroll
-        for (int q = 0; q < 8; ++q) s[(l & 15) * WS_LD + (l >> 4) + 4 * q] = r[q];
-    }
+// LDS index of element (x, k) of a chunk (see above).
+__device__ inline int wl_at(int contig_x, int x, int k) {
+    return contig_x ? k * 32 + x : x * 16 + 2 * ((k >> 1) ^ (x & 7)) + (k & 1);
 }
 
-#define WS_PD 2   // default number of 16-deep chunks in flight per wavefront (registers)
+// LDS byte address of a pointer into LDS.
+__device__ inline uint32_t lds_addr(const double* p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) double*)p;
+}
 
-__device__ inline void ws_mma16(dbl4 (&acc)[2][2], const double* sA, const double* sB) {
+// Four LDS reads and the wait for them in one block.  The compiler knows the
+// direct loads write LDS but cannot tell which buffer, so before any LDS read
+// it can see it would wait for every load in flight, the next chunk's too;
+// reads it cannot see leave the waits to wave_seg_t, which knows the order.
+__device__ inline void wl_read4(uint32_t pa0, uint32_t pa1, uint32_t pb0, uint32_t pb1, double& a0, double& a1,
+                                double& b0, double& b1) {
+    asm volatile(
+        "ds_read_b64 %0, %4\n\t"
+        "ds_read_b64 %1, %5\n\t"
+        "ds_read_b64 %2, %6\n\t"
+        "ds_read_b64 %3, %7\n\t"
+        "s_waitcnt lgkmcnt(0)"
+        : "=&v"(a0), "=&v"(a1), "=&v"(b0), "=&v"(b1)
+        : "v"(pa0), "v"(pa1), "v"(pb0), "v"(pb1)
+        : "memory");
+}
+
+// acc += the chunk in buf (A at buf, B at buf + 512).
+__device__ inline void wl_mma16(dbl4 (&acc)[2][2], const double* buf, int ca, int cb) {
     const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
+    const uint32_t sa = lds_addr(buf), sb = lds_addr(buf + 512);
 #pragma unroll
     for (int kk = 0; kk < 16; kk += 4) {
-        const double* pa = sA + (kk + lk) * WS_LD + li;
-        const double* pb = sB + (kk + lk) * WS_LD + li;
-        const double a0 = pa[0], a1 = pa[16], b0 = pb[0], b1 = pb[16];
+        const int k = kk + lk;
+        double a0, a1, b0, b1;
+        wl_read4(sa + 8u * wl_at(ca, li, k), sa + 8u * wl_at(ca, li + 16, k), sb + 8u * wl_at(cb, li, k),
+                 sb + 8u * wl_at(cb, li + 16, k), a0, a1, b0, b1);
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -107,51 +126,62 @@ __device__ inline void ws_mma16(dbl4 (&acc)[2][2], const double* sA, const doubl
     }
 }
 
+// s_waitcnt immediates, gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
+// 6:4, lgkmcnt in 11:8; a counter at its maximum is not waited for.
+//   vmcnt(8), vmcnt(0) (expcnt 7, lgkmcnt 15); lgkmcnt(0) (vmcnt 63, expcnt 7)
+#define WL_VMCNT8 0x0F78
+#define WL_VMCNT0 0x0F70
+#define WL_LGKM0 0xC07F
+
+template <int CA, int CB>
+__device__ inline void wl_issue(const Seg& sg, int ca, int cb, int avalid, int k, double* buf) {
+    wl_fetch<CA>(sg.a, sg.lda, ca, avalid, k, buf);
+    wl_fetch<CB>(sg.b, sg.ldb, cb, 32, k, buf + 512);
+}
+
 // acc += A(:, k0:k1) * B(k0:k1, :) for this wavefront; k0, k1 multiples of 16.
-// sw: this wavefront's LDS area (WS_WAVE_DOUBLES doubles).  Up to PD
-// chunks are being fetched while one is multiplied.
-template <int PD = WS_PD>
-__device__ inline void wave_seg(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1, double* sw) {
-    const int nch = (k1 - k0) >> 4;
+// sw: this wavefront's LDS area (WS_WAVE_DOUBLES doubles), which holds nothing
+// else while this runs.  Chunk c+2 is fetched into the buffer of chunk c
+// once the products of chunk c have read it.  The vmcnt waits assume no other
+// memory access of this wavefront is issued in between (loads issued before
+// are older and complete first).
+template <int CA, int CB>
+__device__ inline void wave_seg_t(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1, double* sw) {
+    const int nch = __builtin_amdgcn_readfirstlane((k1 - k0) >> 4);
     if (nch <= 0) return;
-    const int ca = !sg.ta, cb = sg.tb;   // A normal / B transposed: contiguous along x
-    double* sA = sw;
-    double* sB = sw + 16 * WS_LD;
-    double ra[PD][8], rb[PD][8];
-#pragma unroll
-    for (int p = 0; p < PD; ++p) {
-        if (p < nch) {
-            ws_fetch(sg.a, sg.lda, ca, sg.avalid, k0 + 16 * p, sg.ca, ra[p]);
-            ws_fetch(sg.b, sg.ldb, cb, 32, k0 + 16 * p, sg.cb, rb[p]);
+    const int ca = __builtin_amdgcn_readfirstlane(!sg.ta), cb = __builtin_amdgcn_readfirstlane(sg.tb);
+    const int avalid = __builtin_amdgcn_readfirstlane(sg.avalid);
+    // the previous user of this LDS area has read it
+    __builtin_amdgcn_s_waitcnt(WL_LGKM0);
+    __builtin_amdgcn_wave_barrier();
+    wl_issue<CA, CB>(sg, ca, cb, avalid, k0, sw);
+    if (nch > 1) wl_issue<CA, CB>(sg, ca, cb, avalid, k0 + 16, sw + WS_CHUNK_DOUBLES);
+    for (int c = 0; c < nch; ++c) {
+        double* buf = sw + (c & 1) * WS_CHUNK_DOUBLES;
+        // chunk c has landed in LDS (chunk c+1's 8 loads may still fly)
+        if (c + 1 < nch) __builtin_amdgcn_s_waitcnt(WL_VMCNT8);
+        else __builtin_amdgcn_s_waitcnt(WL_VMCNT0);
+        __builtin_amdgcn_wave_barrier();
+        asm volatile("" ::: "memory");
+        wl_mma16(acc, buf, ca, cb);
+        if (c + 2 < nch) {
+            // every read of this buffer has returned before it is refilled
+            __builtin_amdgcn_s_waitcnt(WL_LGKM0);
+            __builtin_amdgcn_wave_barrier();
+            asm volatile("" ::: "memory");
+            wl_issue<CA, CB>(sg, ca, cb, avalid, k0 + 16 * (c + 2), buf);
         }
     }
-    int it = 0;
-    for (; it + PD <= nch; it += PD) {
-#pragma unroll
-        for (int p = 0; p < PD; ++p) {
-            wave_lds_sync();
-            ws_stash(sA, ca, ra[p]);
-            ws_stash(sB, cb, rb[p]);
-            wave_lds_sync();
-            const int nx = it + p + PD;
-            if (nx < nch) {
-                ws_fetch(sg.a, sg.lda, ca, sg.avalid, k0 + 16 * nx, sg.ca, ra[p]);
-                ws_fetch(sg.b, sg.ldb, cb, 32, k0 + 16 * nx, sg.cb, rb[p]);
-            }
-            ws_mma16(acc, sA, sB);
-        }
-    }
-#pragma unroll
-    for (int p = 0; p < PD; ++p) {
-        if (it + p < nch) {
-            wave_lds_sync();
-            ws_stash(sA, ca, ra[p]);
-            ws_stash(sB, cb, rb[p]);
-            wave_lds_sync();
-            ws_mma16(acc, sA, sB);
-        }
-    }
-    wave_lds_sync();
+    __builtin_amdgcn_s_waitcnt(WL_LGKM0);
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ inline void wave_seg(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1, double* sw) {
+    const int c = __builtin_amdgcn_readfirstlane((sg.ca ? 1 : 0) | (sg.cb ? 2 : 0));
+    if (c == 1) wave_seg_t<1, 0>(acc, sg, k0, k1, sw);
+    else if (c == 2) wave_seg_t<0, 1>(acc, sg, k0, k1, sw);
+    else if (c == 3) wave_seg_t<1, 1>(acc, sg, k0, k1, sw);
+    else wave_seg_t<0, 0>(acc, sg, k0, k1, sw);
 }
 
 // Run this wavefront's share of a reduction made of nseg segments of total
@@ -160,13 +190,13 @@ __device__ inline void wave_seg(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1
 // smem: WS_SMEM_DOUBLES doubles.
 // Only the range [kbeg, kend) of the reduction is done when kend >= 0
 // (multiples of 16).
-template <int PD = WS_PD, class F>
+template <class F>
 __device__ inline void wave_segs(dbl4 (&acc)[2][2], int nseg, int ktot, double* smem, F&& seg, int kbeg = 0,
                                  int kend = -1) {
     if (kend < 0) kend = ktot;
     const int chunks = (kend - kbeg) >> 4;
     const int per = (chunks + 3) >> 2;
-    const int w = threadIdx.x >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     int kb = kbeg + 16 * per * w, ke = kbeg + 16 * per * (w + 1);
     if (ke > kend) ke = kend;
     if (kb > kend) kb = kend;
@@ -176,7 +206,7 @@ __device__ inline void wave_segs(dbl4 (&acc)[2][2], int nseg, int ktot, double* 
         const Seg sg = seg(q);
         const int lo = kb > s0 ? kb : s0;
         const int hi = ke < s0 + sg.K ? ke : s0 + sg.K;
-        if (lo < hi) wave_seg<PD>(acc, sg, lo - s0, hi - s0, sw);
+        if (lo < hi) wave_seg(acc, sg, lo - s0, hi - s0, sw);
         s0 += sg.K;
     }
 }
