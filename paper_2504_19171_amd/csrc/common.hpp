@@ -15,6 +15,7 @@ struct Lay {
     int bt;            // B: tile half-bandwidth
     int ap;            // arrow rows rounded up to 16 (0 when there is no arrow)
     int a;             // arrow rows
+    int p2s;           // parts of each Phase 2 output's sum: 3, or 2 (k = J+2 joins the far part)
 
     // Offset (in doubles) of band tile (J+d, J).
     __host__ __device__ int64_t band(int64_t J, int d) const {

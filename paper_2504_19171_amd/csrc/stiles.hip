@@ -49,12 +49,26 @@ static int make_layout(int64_t n, int64_t bandwidth, int64_t arrow, int32_t tile
     return 0;
 }
 
+// Parts of the Phase 2 sums: two (measured: as fast as three at tile 256,
+// faster at 128 and, by a fifth in the batched form, at 64, where the extra
+// tasks of the three-part form cost more than the shorter chain saves).
+// STILES_P2_SPLIT=3 selects the three-part form (measurement and tests).
+static int p2_split_for(int tile) {
+    (void)tile;
+    if (const char* e = getenv("STILES_P2_SPLIT")) {
+        const int v = atoi(e);
+        if (v == 2 || v == 3) return v;
+    }
+    return 2;
+}
+
 static Lay to_dev(const stiles_layout& s) {
     Lay l;
     l.nb = s.nb; l.w = s.w; l.nt = s.nt;
     l.off_band = s.off_band; l.off_arrow = s.off_arrow; l.off_corner = s.off_corner;
     l.total = s.total_doubles;
     l.b = s.tile; l.bt = s.bt; l.ap = s.arrow_ld; l.a = (int)s.arrow;
+    l.p2s = p2_split_for(s.tile);
     return l;
 }
 
@@ -874,6 +888,11 @@ __global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, La
 //   k = J+2: final once column J+2 is done;
 //   k = J+1: final once column J+1's off-diagonal tiles (rows i far) or its
 //     diagonal tile (row J+1) are.
+// With two parts (Lay::p2s == 2) the k = J+2 term stays in the far parts:
+// EA and E1A sum over k = J+2.., EB and E1B have no tasks, EA(J) waits for
+// done(J+2) and E1A(J) for L1(J+1) and far(J+1), L and L1 read the partial of
+// EA and E1A, and the group order is [EA(G-1), L(G), L1(G), E1A(G-1), DA(G),
+// DB(G)].
 // Every task is a 32 x 32 block whose reduction is spread over the 4
 // wavefronts of a workgroup, so that the tasks on the dependency chain stay
 // short ("far rows" = tiles J+2..J+s and the arrow):
@@ -925,10 +944,11 @@ __host__ __device__ inline P2Counts p2_counts(const Lay& L, int64_t J) {
     const int C32 = L.b / 32;
     const int far = s > 1 ? s - 1 : 0;
     const int nf32 = far * C32 + (L.ap + 31) / 32;
+    const bool three = L.p2s == 3;
     c.n[P2_EA] = nf32 * C32;
-    c.n[P2_EB] = s >= 2 ? nf32 * C32 : 0;
+    c.n[P2_EB] = three && s >= 2 ? nf32 * C32 : 0;
     c.n[P2_E1A] = s >= 1 ? C32 * C32 : 0;
-    c.n[P2_E1B] = s >= 2 ? C32 * C32 : 0;
+    c.n[P2_E1B] = three && s >= 2 ? C32 * C32 : 0;
     c.n[P2_L] = s >= 1 ? nf32 * C32 : 0;
     c.n[P2_L1] = s >= 1 ? C32 * C32 : 0;
     c.n[P2_DA] = C32 * (C32 + 1) / 2;
@@ -936,13 +956,16 @@ __host__ __device__ inline P2Counts p2_counts(const Lay& L, int64_t J) {
     return c;
 }
 
-// Slot i of group G: the kind and the tile column offset (0 or -1) of its tasks.
+// Slot i of group G: the kind and the tile column offset (0 or -1) of its
+// tasks (with two parts, EB and E1B come last and have no tasks).
 #define P2_SLOTS 8
-__host__ __device__ inline void p2_slot(int i, int& kind, int& dj) {
-    const int k[P2_SLOTS] = {P2_EA, P2_L, P2_E1B, P2_E1A, P2_EB, P2_L1, P2_DA, P2_DB};
-    const int d[P2_SLOTS] = {-1, 0, 0, -1, -1, 0, 0, 0};
-    kind = k[i];
-    dj = d[i];
+__host__ __device__ inline void p2_slot(const Lay& L, int i, int& kind, int& dj) {
+    const int k3[P2_SLOTS] = {P2_EA, P2_L, P2_E1B, P2_E1A, P2_EB, P2_L1, P2_DA, P2_DB};
+    const int d3[P2_SLOTS] = {-1, 0, 0, -1, -1, 0, 0, 0};
+    const int k2[P2_SLOTS] = {P2_EA, P2_L, P2_L1, P2_E1A, P2_DA, P2_DB, P2_EB, P2_E1B};
+    const int d2[P2_SLOTS] = {-1, 0, 0, -1, 0, 0, -1, 0};
+    kind = L.p2s == 3 ? k3[i] : k2[i];
+    dj = L.p2s == 3 ? d3[i] : d2[i];
 }
 
 // Tasks in group G (see the ticket order above).
@@ -1031,8 +1054,9 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
     // the reduction: band tiles J+e0 .. J+e0+nband-1, then the arrow if karw
     int e0, nband;
     bool karw;
+    const int ef = L.p2s == 3 ? 3 : 2;   // first band tile of the far parts
     switch (kind) {
-        case P2_EA: case P2_E1A: e0 = 3; nband = s > 2 ? s - 2 : 0; karw = L.ap > 0; break;
+        case P2_EA: case P2_E1A: e0 = ef; nband = s >= ef ? s - ef + 1 : 0; karw = L.ap > 0; break;
         case P2_EB: case P2_E1B: e0 = 2; nband = 1; karw = false; break;
         case P2_DA: e0 = 2; nband = far; karw = L.ap > 0; break;
         default: e0 = 1; nband = 1; karw = false;   // L, L1, DB
@@ -1154,7 +1178,7 @@ __device__ inline void p2_run(const P2& p, const Sched& sc, double* smem, int* s
         }
         for (int i = 0; kind < 0 && i < P2_SLOTS; ++i) {
             int k, dj;
-            p2_slot(i, k, dj);
+            p2_slot(L, i, k, dj);
             if (G + dj < 0) continue;
             const int n = p2_counts(L, G + dj).n[k];
             if (u < n) { kind = k; J = G + dj; }
@@ -1165,11 +1189,18 @@ __device__ inline void p2_run(const P2& p, const Sched& sc, double* smem, int* s
         // dependencies, all polled together
         SchedDeps dp;
         dp.n = 0;
-        const bool two = L.s(J) >= 2;
+        const bool three = L.p2s == 3;
+        const bool two = three && L.s(J) >= 2;   // EB / E1B hold the partial
         switch (kind) {
-            case P2_EA: p2_dep_offdiag(p, dp, J + 2); break;
+            case P2_EA:
+                if (three) p2_dep_offdiag(p, dp, J + 2);
+                else p2_dep_done(p, dp, J + 2);
+                break;
             case P2_EB: p2_dep_done(p, dp, J + 2); p2_dep_all(p, dp, P2_EA, J); break;
-            case P2_E1A: p2_dep_far(p, dp, J + 1); break;
+            case P2_E1A:
+                if (!three) p2_dep_all(p, dp, P2_L1, J + 1);
+                p2_dep_far(p, dp, J + 1);
+                break;
             case P2_E1B: p2_dep_all(p, dp, P2_L1, J + 1); p2_dep_all(p, dp, P2_E1A, J); break;
             case P2_L: p2_dep_offdiag(p, dp, J + 1); p2_dep_all(p, dp, two ? P2_EB : P2_EA, J); break;
             case P2_L1: p2_dep_done(p, dp, J + 1); p2_dep_all(p, dp, two ? P2_E1B : P2_E1A, J); break;

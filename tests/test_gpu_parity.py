@@ -65,6 +65,29 @@ def test_factor_and_selinv_match_oracle(torch_cuda, oracle_mod, nb, w, a, b):
     assert lderr <= LOGDET_TOL
 
 
+@pytest.mark.parametrize("nb,w,a,b", [(2000, 32, 20, 64), (1100, 700, 45, 256), (777, 100, 33, 128)])
+def test_three_part_phase2_matches_oracle(torch_cuda, oracle_mod, monkeypatch, nb, w, a, b):
+    """The Phase 2 form that sums each output in three parts (k = J+2 taken
+    apart from the far part; STILES_P2_SPLIT=3) against the oracle, and
+    against the default two-part form within the same tolerance."""
+    from gpu_util import run_gpu, sigma_error, SIGMA_TOL
+    M = inputs.arrowhead_spd(nb, w, a, seed=3000 + nb)
+    print(f"three-part nb={nb} w={w} a={a} b={b}", flush=True)
+    r2 = run_gpu(M, b)
+    monkeypatch.setenv("STILES_P2_SPLIT", "3")
+    r3 = run_gpu(M, b)
+    monkeypatch.delenv("STILES_P2_SPLIT")
+    assert r3["info"] == 0 and r3["sinfo"] == 0
+    f = oracle_mod.cholesky(M.ab, M.P, M.C)
+    S = oracle_mod.selinv(f, b)
+    serr, drel = sigma_error(r3["S"], r3["lay"], S)
+    print(f"  Sigma err {serr:.2e}, diag {drel:.2e}", flush=True)
+    assert serr <= SIGMA_TOL and drel <= SIGMA_TOL
+    assert np.array_equal(r2["L"], r3["L"])          # the factor does not depend on it
+    d = np.abs(r2["S"] - r3["S"])
+    assert np.all(np.isfinite(r3["S"])) and float(np.max(d)) <= 1e-9 * float(np.max(np.abs(r2["S"])))
+
+
 def test_unused_tiles_and_padding(torch_cuda, oracle_mod):
     """Band tiles beyond the matrix stay 0; pad rows of Sigma are identity."""
     from gpu_util import run_gpu
