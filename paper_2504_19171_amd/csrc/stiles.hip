@@ -642,12 +642,15 @@ __device__ inline bool col_task(ColSmem& sm, int& sh, double* Lm, const Lay& L, 
     int* fpo = cf + CF_PO;
     int* ftr = cf + CF_TR;
     {
+        TRACE(gt, 3, (unsigned long long)(t == 0 ? 0 : (t <= ntr ? 1 : 2)) | ((unsigned long long)J << 8) |
+                         ((unsigned long long)t << 40));
         if (t == 0) {
             if (upd) {
                 const int need = (int)(J - imax64(0, J - L.bt));
                 for (int i = 0; i < C64 && need > 0; ++i)
                     if (!col_wait(st, upd + upd_band(L, J, 0, i, 0), i + 1, need, &sh)) return false;
             }
+            TRACE(gt, 1, wall_clock64());
             int fail;
             double ls, lc;
             potrf3(Lm + L.band(J, 0), L.b, L.b, Yd, sm.po, &fail, &ls, &lc, gt == st.withhold ? nullptr : fpo);
@@ -674,12 +677,15 @@ __device__ inline bool col_task(ColSmem& sm, int& sh, double* Lm, const Lay& L, 
                 }
                 if (!ok) return false;
             }
+            TRACE(gt, 1, wall_clock64());
             if (!tr_panel(C, ld, Lm + L.band(J, 0), Yd, L.b, fpo, ftr + g, st, sm.tr, gt)) return false;
         } else {
             const UpBlock u = col_up_decode(Lm, L, J, t - 1 - ntr, upd);
+            TRACE(gt, 1, wall_clock64());
             if (!col_update(u, ftr, L.b / 16, st, &sh, gt)) return false;
         }
     }
+    TRACE(gt, 2, wall_clock64());
     return true;
 }
 // The whole factor of the band tile columns in one persistent launch.
@@ -700,6 +706,7 @@ __global__ __launch_bounds__(P3_NT) void k_factor_all(double* Lm, Lay L, double*
     for (;;) {
         const int g = sched_next(sc, ntot, &sh);
         if (g < 0) return;
+        TRACE(g, 0, wall_clock64());
         int lo = 0, hi = (int)N;
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
