@@ -55,41 +55,47 @@ __device__ inline void gacc_zero(GAcc& g) {
 
 // Fetch 4 doubles of chunk k0 of operand "A-like" (x = output row index) into r.
 // trans == 0: element (x, k) at p[x + k*ld]; trans == 1: at p[k + x*ld].
+// The loads are unconditional (a row x >= valid reads row valid-1, inside the
+// operand) and gb_stash zeroes those rows: a load guarded by a branch, or
+// whose value is selected right away, makes the compiler wait for every load
+// in flight there, and the next chunk's loads would no longer overlap the
+// products of the current one.
 __device__ inline void gb_fetch(const Opnd& o, int k0, double r[4], bool a_side) {
     const int t = threadIdx.x;
     // For the B operand the roles of "normal" and "transposed" swap: B(k, j)
     // normal is p[k + j*ld], i.e. contiguous along k like a transposed A.
     const int contig_x = a_side ? !o.trans : o.trans;
-    // offsets stay inside one operand tile (< 2^31 doubles)
+    // offsets stay inside one operand tile (< 2^29 doubles)
     const double* b = uniform_ptr(o.p);
     const int ldi = (int)o.ld;
+    const int last = (o.valid > 0 ? o.valid : 1) - 1;
     if (contig_x) {
-        const int x = t & 63;
-        const bool ok = x < o.valid;
-        const int off = x + (k0 + (t >> 6)) * ldi;
+        const int x = imin_(t & 63, last);
+        const uint32_t off = (uint32_t)(x + (k0 + (t >> 6)) * ldi);
 #pragma unroll
-        for (int q = 0; q < 4; ++q) r[q] = ok ? b[off + 4 * q * ldi] : 0.0;
+        for (int q = 0; q < 4; ++q) r[q] = ld_s(b, off + (uint32_t)(4 * q * ldi));
     } else {
         const int k = t & 15;
         const int x0 = t >> 4;
-        const int off = (k0 + k) + x0 * ldi;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) r[q] = (x0 + 16 * q < o.valid) ? b[off + 16 * q * ldi] : 0.0;
+        for (int q = 0; q < 4; ++q) r[q] = ld_s(b, (uint32_t)((k0 + k) + imin_(x0 + 16 * q, last) * ldi));
     }
 }
 
-// Store the fetched values as s[k][x] (leading dimension GB_LDA).
+// Store the fetched values as s[k][x] (leading dimension GB_LDA), rows x >=
+// valid as 0.
 __device__ inline void gb_stash(const Opnd& o, double* s, const double r[4], bool a_side) {
     const int t = threadIdx.x;
     const int contig_x = a_side ? !o.trans : o.trans;
     if (contig_x) {
         const int x = t & 63;
+        const bool ok = x < o.valid;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[((t >> 6) + 4 * q) * GB_LDA + x] = r[q];
+        for (int q = 0; q < 4; ++q) s[((t >> 6) + 4 * q) * GB_LDA + x] = ok ? r[q] : 0.0;
     } else {
         const int k = t & 15;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) s[k * GB_LDA + (t >> 4) + 16 * q] = r[q];
+        for (int q = 0; q < 4; ++q) s[k * GB_LDA + (t >> 4) + 16 * q] = ((t >> 4) + 16 * q < o.valid) ? r[q] : 0.0;
     }
 }
 
