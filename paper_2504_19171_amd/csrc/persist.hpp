@@ -86,43 +86,51 @@ __device__ inline bool sched_wait(const Sched& s, int* flag, int target, int* sh
 // waiting workgroup: the polls of hundreds of waiting workgroups share the
 // memory channels of a few counters).  Returns false if the kernel must stop.
 #define SCHED_MAX_DEPS 3
+// (three named slots rather than an array: an array indexed by the running
+// count would live in scratch memory, whose loads count on the same memory
+// counter as the task's own loads)
 struct SchedDeps {
-    int* flag[SCHED_MAX_DEPS];
-    int target[SCHED_MAX_DEPS];
+    int* f0;
+    int* f1;
+    int* f2;
+    int t0, t1, t2;
     int n;
 };
 __device__ inline void deps_add(SchedDeps& d, int* flag, int target) {
-    d.flag[d.n] = flag;
-    d.target[d.n] = target;
+    if (d.n == 0) { d.f0 = flag; d.t0 = target; }
+    else if (d.n == 1) { d.f1 = flag; d.t1 = target; }
+    else { d.f2 = flag; d.t2 = target; }
     ++d.n;
+}
+__device__ inline bool sched_wait_deps_one(const Sched& s, const int* f, int target, int64_t& t0, unsigned& polls,
+                                           int x) {
+    while (x < target) {
+        if (t0 < 0) t0 = wall_clock64();
+        // the error word is one address for every workgroup: read it on every
+        // 16th poll only
+        if ((polls++ & 15) == 0 && ld_coh_i(s.err) != 0) return false;
+        if (wall_clock64() - t0 > s.spin_limit) {
+            set_error_once(s.err, STILES_ETIMEOUT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(2);
+        x = ld_coh_i(f);
+    }
+    return true;
 }
 __device__ inline bool sched_wait_deps(const Sched& s, const SchedDeps& d, int* sh) {
     if (threadIdx.x == 0) {
-        int ok = 1;
-        int v[SCHED_MAX_DEPS];
-#pragma unroll
-        for (int i = 0; i < SCHED_MAX_DEPS; ++i) v[i] = i < d.n ? ld_coh_i(d.flag[i]) : 0;
+        int v0 = 0, v1 = 0, v2 = 0;
+        if (d.n > 0) v0 = ld_coh_i(d.f0);
+        if (d.n > 1) v1 = ld_coh_i(d.f1);
+        if (d.n > 2) v2 = ld_coh_i(d.f2);
         int64_t t0 = -1;
         unsigned polls = 0;
-#pragma unroll
-        for (int i = 0; i < SCHED_MAX_DEPS; ++i) {
-            if (i >= d.n || !ok) continue;
-            int x = v[i];
-            while (x < d.target[i]) {
-                if (t0 < 0) t0 = wall_clock64();
-                // the error word is one address for every workgroup: read it
-                // on every 16th poll only
-                if ((polls++ & 15) == 0 && ld_coh_i(s.err) != 0) { ok = 0; break; }
-                if (wall_clock64() - t0 > s.spin_limit) {
-                    set_error_once(s.err, STILES_ETIMEOUT);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(2);
-                x = ld_coh_i(d.flag[i]);
-            }
-        }
-        *sh = ok;
+        bool ok = true;
+        if (d.n > 0) ok = sched_wait_deps_one(s, d.f0, d.t0, t0, polls, v0);
+        if (ok && d.n > 1) ok = sched_wait_deps_one(s, d.f1, d.t1, t0, polls, v1);
+        if (ok && d.n > 2) ok = sched_wait_deps_one(s, d.f2, d.t2, t0, polls, v2);
+        *sh = ok ? 1 : 0;
     }
     __syncthreads();
     const bool ok = __builtin_amdgcn_readfirstlane(*sh) != 0;

@@ -963,16 +963,51 @@ __host__ __device__ inline P2Counts p2_counts(const Lay& L, int64_t J) {
     return c;
 }
 
+// Task count of one kind (a switch rather than indexing P2Counts::n with a
+// run-time kind, which would put the array in scratch memory).
+__host__ __device__ inline int p2_count(const Lay& L, int64_t J, int kind) {
+    const P2Counts c = p2_counts(L, J);
+    switch (kind) {
+        case P2_EA: return c.n[P2_EA];
+        case P2_EB: return c.n[P2_EB];
+        case P2_E1A: return c.n[P2_E1A];
+        case P2_E1B: return c.n[P2_E1B];
+        case P2_L: return c.n[P2_L];
+        case P2_L1: return c.n[P2_L1];
+        case P2_DA: return c.n[P2_DA];
+        default: return c.n[P2_DB];
+    }
+}
+
 // Slot i of group G: the kind and the tile column offset (0 or -1) of its
 // tasks (with two parts, EB and E1B come last and have no tasks).
 #define P2_SLOTS 8
+// (a switch, not tables: a table indexed at run time would live in scratch
+// memory)
 __host__ __device__ inline void p2_slot(const Lay& L, int i, int& kind, int& dj) {
-    const int k3[P2_SLOTS] = {P2_EA, P2_L, P2_E1B, P2_E1A, P2_EB, P2_L1, P2_DA, P2_DB};
-    const int d3[P2_SLOTS] = {-1, 0, 0, -1, -1, 0, 0, 0};
-    const int k2[P2_SLOTS] = {P2_EA, P2_L, P2_L1, P2_E1A, P2_DA, P2_DB, P2_EB, P2_E1B};
-    const int d2[P2_SLOTS] = {-1, 0, 0, -1, 0, 0, -1, 0};
-    kind = L.p2s == 3 ? k3[i] : k2[i];
-    dj = L.p2s == 3 ? d3[i] : d2[i];
+    if (L.p2s == 3) {
+        switch (i) {
+            case 0: kind = P2_EA; dj = -1; break;
+            case 1: kind = P2_L; dj = 0; break;
+            case 2: kind = P2_E1B; dj = 0; break;
+            case 3: kind = P2_E1A; dj = -1; break;
+            case 4: kind = P2_EB; dj = -1; break;
+            case 5: kind = P2_L1; dj = 0; break;
+            case 6: kind = P2_DA; dj = 0; break;
+            default: kind = P2_DB; dj = 0;
+        }
+    } else {
+        switch (i) {
+            case 0: kind = P2_EA; dj = -1; break;
+            case 1: kind = P2_L; dj = 0; break;
+            case 2: kind = P2_L1; dj = 0; break;
+            case 3: kind = P2_E1A; dj = -1; break;
+            case 4: kind = P2_DA; dj = 0; break;
+            case 5: kind = P2_DB; dj = 0; break;
+            case 6: kind = P2_EB; dj = -1; break;
+            default: kind = P2_E1B; dj = 0;
+        }
+    }
 }
 
 // Tasks in group G (see the ticket order above).
@@ -1026,7 +1061,7 @@ __device__ inline void p2_far_row(const Lay& L, int s, int rbg, int rb, int& d, 
 // Every task of the given kind and tile column finished (nothing to wait for
 // past the last column).
 __device__ inline void p2_dep_all(const P2& p, SchedDeps& d, int kind, int64_t J) {
-    if (J < p.L.nt) deps_add(d, &p.cnt[kind * p.L.nt + J], p2_counts(p.L, J).n[kind]);
+    if (J < p.L.nt) deps_add(d, &p.cnt[kind * p.L.nt + J], p2_count(p.L, J, kind));
 }
 // done(J): all of column J final.
 __device__ inline void p2_dep_done(const P2& p, SchedDeps& d, int64_t J) {
@@ -1094,11 +1129,16 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
     const bool diag = (kind >= P2_DA) && rb == cb;
     // the partial already stored (EB, E1B, L, L1, DB) is final once the task
     // runs: read it now so its round trip overlaps the products
-    double ov[4];
+    // (unconditional loads from inside the block, the unused ones dropped
+    // when the partial is applied: a load under a branch would make the
+    // compiler wait for it before the products)
+    double ov[4] = {0.0, 0.0, 0.0, 0.0};
+    if (!zero_base) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int e = threadIdx.x + 256 * q, i = e & 31, j = e >> 5;
-        ov[q] = (zero_base || i >= mv || (diag && i < j)) ? 0.0 : ld_coh(O + i + (int64_t)j * ldo);
+        for (int q = 0; q < 4; ++q) {
+            const int e = threadIdx.x + 256 * q, i = imin_(e & 31, mv - 1), j = e >> 5;
+            ov[q] = ld_coh(O + i + (int64_t)j * ldo);
+        }
     }
     dbl4 acc[2][2];
 #pragma unroll
@@ -1130,7 +1170,7 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
     for (int q = 0; q < 4; ++q) {
         const int e = threadIdx.x + 256 * q, i = e & 31, j = e >> 5;
         if (i >= mv || (diag && i < j)) continue;
-        red[j * WR_LD + i] = ov[q] - red[j * WR_LD + i];
+        red[j * WR_LD + i] = (zero_base ? 0.0 : ov[q]) - red[j * WR_LD + i];
     }
     __syncthreads();
     for (int e = threadIdx.x; e < 1024; e += 256) {
@@ -1187,7 +1227,7 @@ __device__ inline void p2_run(const P2& p, const Sched& sc, double* smem, int* s
             int k, dj;
             p2_slot(L, i, k, dj);
             if (G + dj < 0) continue;
-            const int n = p2_counts(L, G + dj).n[k];
+            const int n = p2_count(L, G + dj, k);
             if (u < n) { kind = k; J = G + dj; }
             else u -= n;
         }
