@@ -1082,11 +1082,25 @@ __device__ inline void p2_dep_offdiag(const P2& p, SchedDeps& d, int64_t J) {
     }
 }
 
-#define P2_SMEM_DOUBLES (WS_SMEM_DOUBLES + 32 * WR_LD)
-#define P2_WG_PER_CU 2
+// LDS of a Phase 2 workgroup: the wavefronts' staging areas, which
+// wave_reduce reuses for the partial blocks (the larger of the two), then the
+// reduced block.  The single-matrix kernel, bound by its dependency chain,
+// runs two workgroups per CU with 16-deep chunks; the batched one, which has
+// the independent work of many matrices to overlap, three with 8-deep chunks
+// (measured: 125 against 140 ms per batched pass; the single matrix's Phase
+// 2 took 23 ms instead of 17 that way).
+template <int KC>
+struct P2Cfg {
+    static constexpr int STAGE = WS<KC>::SMEM > WR_SMEM_DOUBLES ? WS<KC>::SMEM : WR_SMEM_DOUBLES;
+    static constexpr int SMEM = STAGE + 32 * WR_LD;
+    static constexpr int WG_PER_CU = KC == 16 ? 2 : 3;
+};
+#define P2_KC_SINGLE 16
+#define P2_KC_BATCHED 8
 
 // One Phase 2 task: a 32 x 32 output block, its reduction spread over the 4
 // wavefronts.
+template <int KC>
 __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, int u, bool mirror_da, double* smem,
                                            double* red, int t) {
     const Lay& L = p.L;
@@ -1145,7 +1159,7 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
     for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) acc[i][j] = dbl4{0.0, 0.0, 0.0, 0.0};
-    wave_segs(acc, nseg, ktot, smem, [&](int q) {
+    wave_segs<KC>(acc, nseg, ktot, smem, [&](int q) {
         const int e = (q < nband) ? e0 + q : ARW;
         if (rowtask) {
             const double* a; int64_t lda; int ta, av;
@@ -1187,8 +1201,9 @@ __device__ __forceinline__ void p2_task_small(const P2& p, int kind, int64_t J, 
     TRACE(t, 6, wall_clock64());
 }
 
+template <int KC>
 __device__ inline void p2_run(const P2& p, const Sched& sc, double* smem, int* sh) {
-    double* red = smem + WS_SMEM_DOUBLES;
+    double* red = smem + P2Cfg<KC>::STAGE;
     const Lay& L = p.L;
     const int64_t N = L.nt;
     for (;;) {
@@ -1257,7 +1272,7 @@ __device__ inline void p2_run(const P2& p, const Sched& sc, double* smem, int* s
         if (!sched_wait_deps(sc, dp, &sh[1])) break;
         TRACE(t, 1, wall_clock64());
 
-        p2_task_small(p, kind, J, u, L.s(J) == 0, smem, red, t);
+        p2_task_small<KC>(p, kind, J, u, L.s(J) == 0, smem, red, t);
         sched_signal(sc, my, t);
         TRACE(t, 2, wall_clock64());
         TRACE(t, 3, (unsigned long long)kind | ((unsigned long long)J << 8) | ((unsigned long long)blockIdx.x << 40));
@@ -1265,9 +1280,9 @@ __device__ inline void p2_run(const P2& p, const Sched& sc, double* smem, int* s
     }
 }
 __global__ __launch_bounds__(NT) void k_phase2(P2 p, Sched sc) {
-    __shared__ double smem[P2_SMEM_DOUBLES];
+    __shared__ double smem[P2Cfg<P2_KC_SINGLE>::SMEM];
     __shared__ int sh[2];
-    p2_run(p, sc, smem, sh);
+    p2_run<P2_KC_SINGLE>(p, sc, smem, sh);
 }
 
 __global__ void k_selinv_final(const int* info_ws, const int* err, int* info) {
@@ -1494,7 +1509,7 @@ __global__ __launch_bounds__(NT) void kb_lauum(BArgs a) {
 // Phase 2 of every matrix in one persistent launch: each matrix runs on its
 // own share of the workgroups, with its own tickets.
 __global__ __launch_bounds__(NT) void kb_phase2(BArgs a) {
-    __shared__ double smem[P2_SMEM_DOUBLES];
+    __shared__ double smem[P2Cfg<P2_KC_BATCHED>::SMEM];
     __shared__ int sh[2];
     BATCH_DECODE(a, I, bid, nblk);
     const SelinvWs v = selinv_ws(I.L, I.ws);
@@ -1503,7 +1518,7 @@ __global__ __launch_bounds__(NT) void kb_phase2(BArgs a) {
     sc.err = v.err;
     sc.spin_limit = a.spin_limit;
     sc.withhold = -1;
-    p2_run(make_p2(I.S, v, I.L, I.p2_tasks), sc, smem, sh);
+    p2_run<P2_KC_BATCHED>(make_p2(I.S, v, I.L, I.p2_tasks), sc, smem, sh);
 }
 
 __global__ void kb_selinv_final(const BInst* bi) {
@@ -2129,7 +2144,7 @@ static int selinv_impl(const double* Lm, double* S, const stiles_layout& lay, in
     sc.withhold = debug_withhold();
     LAUNCH(STILES_TK_OTHER, k_p2_setup, dim3(1), dim3(NT), 0, st, p, sc.ticket, sc.err);
     if (ntasks > 0) {
-        const int grid = (int)std::min<int64_t>(ntasks, P2_WG_PER_CU * (int64_t)di.cus);
+        const int grid = (int)std::min<int64_t>(ntasks, P2Cfg<P2_KC_SINGLE>::WG_PER_CU * (int64_t)di.cus);
         LAUNCH(STILES_TK_PHASE2, k_phase2, dim3(grid), dim3(NT), 0, st, p, sc);
     }
     LAUNCH(STILES_TK_OTHER, k_selinv_final, dim3(1), dim3(64), 0, st, (const int*)v.winfo, (const int*)v.err,
@@ -2478,7 +2493,7 @@ static int selinv_batched_impl(const stiles_batch_item* items, int32_t count, vo
     // counts, at least one per matrix
     t.start(segs.size());
     {
-        const int64_t total = std::min<int64_t>(sum_tasks, P2_WG_PER_CU * (int64_t)di.cus);
+        const int64_t total = std::min<int64_t>(sum_tasks, P2Cfg<P2_KC_BATCHED>::WG_PER_CU * (int64_t)di.cus);
         for (int k = 0; k < count; ++k) {
             const int64_t want = total * bi[k].p2_tasks / std::max<int64_t>(1, sum_tasks);
             t.add(segs, k, (int)std::max<int64_t>(1, std::min<int64_t>(bi[k].p2_tasks, want)));

@@ -35,29 +35,37 @@ __device__ inline Seg mkseg(const double* a, int64_t lda, int ta, const double* 
     return s;
 }
 
-// Per-wavefront LDS staging with direct loads: a 16-deep chunk of A (32 x 16)
-// and of B (16 x 32) goes from memory straight into the wavefront's private
-// LDS area (global_load_lds_dwordx4: lane l's 16 bytes land at 16*l from the
-// instruction's base, 1 KB per instruction, 4 instructions per operand), two
-// chunks in flight in two buffers.  No registers hold data in flight and
-// nothing is copied into LDS by the wavefront itself.  Each lane fetches two
-// consecutive doubles along the contiguous dimension of its operand:
+// Per-wavefront LDS staging with direct loads: a KC-deep chunk of A (32 x KC)
+// and of B (KC x 32), KC = 16 or 8, goes from memory straight into the
+// wavefront's private LDS area (global_load_lds_dwordx4: lane l's 16 bytes
+// land at 16*l from the instruction's base, 1 KB per instruction, KC/4
+// instructions per operand), two chunks in flight in two buffers.  No
+// registers hold data in flight and nothing is copied into LDS by the
+// wavefront itself.  Each lane fetches two consecutive doubles along the
+// contiguous dimension of its operand:
 //   contiguous along x (A with ta == 0, B with tb == 1): element (x, k) at
 //     [k*32 + x];
-//   contiguous along k: element (x, k) at [x*16 + 2*((k/2) ^ (x%8)) + k%2]
-//     (the pairs of a row permuted by the row index, so that the 16 rows a
-//     matrix-core operand read touches fall in different LDS banks).
-#define WS_CHUNK_DOUBLES 1024                        // A (512) + B (512)
-#define WS_WAVE_DOUBLES (2 * WS_CHUNK_DOUBLES)       // two buffers
-#define WS_SMEM_DOUBLES (4 * WS_WAVE_DOUBLES)
+//   contiguous along k: element (x, k) at [x*KC + 2*((k/2) ^ s(x)) + k%2],
+//     s(x) = x%8 (KC = 16) or (x/4)%4 (KC = 8): the pairs of a row permuted by
+//     the row index, so that the 16 rows a matrix-core operand read touches
+//     fall in different LDS banks.
+// Sixteen-deep chunks keep fewer waits per product; eight-deep ones halve the
+// LDS area, so that three workgroups fit on one compute unit.
+template <int KC>
+struct WS {
+    static constexpr int CHUNK = 2 * 32 * KC;     // A then B
+    static constexpr int WAVE = 2 * CHUNK;        // two buffers
+    static constexpr int SMEM = 4 * WAVE;         // four wavefronts
+    static constexpr int VMCNT_CHUNK = KC == 16 ? 0x0F78 : 0x0F74;   // s_waitcnt vmcnt(KC/2)
+};
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
-// Issue the loads of one 32 x 16 operand chunk (x = output index, k =
-// reduction index, k0 its first k) into dst (512 doubles of LDS).
+// Issue the loads of one 32 x KC operand chunk (x = output index, k =
+// reduction index, k0 its first k) into dst (32 KC doubles of LDS).
 //   contig_x: element (x, k) at p[x + k*ld], else at p[k + x*ld].
 // COH: device-coherent loads.  Offsets stay inside one operand tile.
-template <int COH>
+template <int KC, int COH>
 __device__ inline void wl_fetch(const double* p, int64_t ld, int contig_x, int valid, int k0, double* dst) {
     const double* b = uniform_ptr(p);
     const int l = threadIdx.x & 63;
@@ -68,23 +76,33 @@ __device__ inline void wl_fetch(const double* p, int64_t ld, int contig_x, int v
         const int x2 = imin_(2 * (l & 15), valid - 2);
         const double* g = b + x2 + (int64_t)(k0 + (l >> 4)) * ldi;
 #pragma unroll
-        for (int q = 0; q < 4; ++q)
+        for (int q = 0; q < KC / 4; ++q)
             __builtin_amdgcn_global_load_lds((const void*)(g + (int64_t)(4 * q) * ldi),
                                              (lds_void_t*)(dst + 128 * q), 16, 0, COH ? 16 : 0);
-    } else {
-        // instruction q: row x = 8q + l/8, pair c = (l%8) ^ (l/8) of k
+    } else if (KC == 16) {
+        // instruction q: row x = 8q + l/8, pair c = (l%8) ^ (x%8) of k
         const int xl = l >> 3, c = (l & 7) ^ xl;
         const double* g = b + (k0 + 2 * c) + (int64_t)xl * ldi;
 #pragma unroll
         for (int q = 0; q < 4; ++q)
             __builtin_amdgcn_global_load_lds((const void*)(g + (int64_t)(8 * q) * ldi),
                                              (lds_void_t*)(dst + 128 * q), 16, 0, COH ? 16 : 0);
+    } else {
+        // instruction q: row x = 16q + l/4, pair c = (l%4) ^ ((x/4)%4) of k
+        const int c = (l & 3) ^ ((l >> 4) & 3);
+        const double* g = b + (k0 + 2 * c) + (int64_t)(l >> 2) * ldi;
+#pragma unroll
+        for (int q = 0; q < 2; ++q)
+            __builtin_amdgcn_global_load_lds((const void*)(g + (int64_t)(16 * q) * ldi),
+                                             (lds_void_t*)(dst + 128 * q), 16, 0, COH ? 16 : 0);
     }
 }
 
 // LDS index of element (x, k) of a chunk (see above).
+template <int KC>
 __device__ inline int wl_at(int contig_x, int x, int k) {
-    return contig_x ? k * 32 + x : x * 16 + 2 * ((k >> 1) ^ (x & 7)) + (k & 1);
+    if (contig_x) return k * 32 + x;
+    return KC == 16 ? x * 16 + 2 * ((k >> 1) ^ (x & 7)) + (k & 1) : x * 8 + 2 * ((k >> 1) ^ ((x >> 2) & 3)) + (k & 1);
 }
 
 // LDS byte address of a pointer into LDS.
@@ -109,16 +127,17 @@ __device__ inline void wl_read4(uint32_t pa0, uint32_t pa1, uint32_t pb0, uint32
         : "memory");
 }
 
-// acc += the chunk in buf (A at buf, B at buf + 512).
-__device__ inline void wl_mma16(dbl4 (&acc)[2][2], const double* buf, int ca, int cb) {
+// acc += the chunk in buf (A at buf, B at buf + 32 KC).
+template <int KC>
+__device__ inline void wl_mma(dbl4 (&acc)[2][2], const double* buf, int ca, int cb) {
     const int l = threadIdx.x & 63, li = l & 15, lk = l >> 4;
-    const uint32_t sa = lds_addr(buf), sb = lds_addr(buf + 512);
+    const uint32_t sa = lds_addr(buf), sb = lds_addr(buf + 32 * KC);
 #pragma unroll
-    for (int kk = 0; kk < 16; kk += 4) {
+    for (int kk = 0; kk < KC; kk += 4) {
         const int k = kk + lk;
         double a0, a1, b0, b1;
-        wl_read4(sa + 8u * wl_at(ca, li, k), sa + 8u * wl_at(ca, li + 16, k), sb + 8u * wl_at(cb, li, k),
-                 sb + 8u * wl_at(cb, li + 16, k), a0, a1, b0, b1);
+        wl_read4(sa + 8u * wl_at<KC>(ca, li, k), sa + 8u * wl_at<KC>(ca, li + 16, k), sb + 8u * wl_at<KC>(cb, li, k),
+                 sb + 8u * wl_at<KC>(cb, li + 16, k), a0, a1, b0, b1);
         acc[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc[0][0], 0, 0, 0);
         acc[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc[0][1], 0, 0, 0);
         acc[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc[1][0], 0, 0, 0);
@@ -128,69 +147,69 @@ __device__ inline void wl_mma16(dbl4 (&acc)[2][2], const double* buf, int ca, in
 
 // s_waitcnt immediates, gfx9 encoding: vmcnt in bits 3:0 and 15:14, expcnt in
 // 6:4, lgkmcnt in 11:8; a counter at its maximum is not waited for.
-//   vmcnt(8), vmcnt(0) (expcnt 7, lgkmcnt 15); lgkmcnt(0) (vmcnt 63, expcnt 7)
-#define WL_VMCNT8 0x0F78
+//   vmcnt(0) (expcnt 7, lgkmcnt 15); lgkmcnt(0) (vmcnt 63, expcnt 7)
 #define WL_VMCNT0 0x0F70
 #define WL_LGKM0 0xC07F
 
-template <int CA, int CB>
+template <int KC, int CA, int CB>
 __device__ inline void wl_issue(const Seg& sg, int ca, int cb, int avalid, int k, double* buf) {
-    wl_fetch<CA>(sg.a, sg.lda, ca, avalid, k, buf);
-    wl_fetch<CB>(sg.b, sg.ldb, cb, 32, k, buf + 512);
+    wl_fetch<KC, CA>(sg.a, sg.lda, ca, avalid, k, buf);
+    wl_fetch<KC, CB>(sg.b, sg.ldb, cb, 32, k, buf + 32 * KC);
 }
 
-// acc += A(:, k0:k1) * B(k0:k1, :) for this wavefront; k0, k1 multiples of 16.
-// sw: this wavefront's LDS area (WS_WAVE_DOUBLES doubles), which holds nothing
+// acc += A(:, k0:k1) * B(k0:k1, :) for this wavefront; k0, k1 multiples of KC.
+// sw: this wavefront's LDS area (WS<KC>::WAVE doubles), which holds nothing
 // else while this runs.  Chunk c+2 is fetched into the buffer of chunk c
 // once the products of chunk c have read it.  The vmcnt waits assume no other
 // memory access of this wavefront is issued in between (loads issued before
 // are older and complete first).
-template <int CA, int CB>
+template <int KC, int CA, int CB>
 __device__ inline void wave_seg_t(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1, double* sw) {
-    const int nch = __builtin_amdgcn_readfirstlane((k1 - k0) >> 4);
+    const int nch = __builtin_amdgcn_readfirstlane((k1 - k0) / KC);
     if (nch <= 0) return;
     const int ca = __builtin_amdgcn_readfirstlane(!sg.ta), cb = __builtin_amdgcn_readfirstlane(sg.tb);
     const int avalid = __builtin_amdgcn_readfirstlane(sg.avalid);
     // the previous user of this LDS area has read it
     __builtin_amdgcn_s_waitcnt(WL_LGKM0);
     __builtin_amdgcn_wave_barrier();
-    wl_issue<CA, CB>(sg, ca, cb, avalid, k0, sw);
-    if (nch > 1) wl_issue<CA, CB>(sg, ca, cb, avalid, k0 + 16, sw + WS_CHUNK_DOUBLES);
+    wl_issue<KC, CA, CB>(sg, ca, cb, avalid, k0, sw);
+    if (nch > 1) wl_issue<KC, CA, CB>(sg, ca, cb, avalid, k0 + KC, sw + WS<KC>::CHUNK);
     for (int c = 0; c < nch; ++c) {
-        double* buf = sw + (c & 1) * WS_CHUNK_DOUBLES;
-        // chunk c has landed in LDS (chunk c+1's 8 loads may still fly)
-        if (c + 1 < nch) __builtin_amdgcn_s_waitcnt(WL_VMCNT8);
+        double* buf = sw + (c & 1) * WS<KC>::CHUNK;
+        // chunk c has landed in LDS (chunk c+1's KC/2 loads may still fly)
+        if (c + 1 < nch) __builtin_amdgcn_s_waitcnt(WS<KC>::VMCNT_CHUNK);
         else __builtin_amdgcn_s_waitcnt(WL_VMCNT0);
         __builtin_amdgcn_wave_barrier();
         asm volatile("" ::: "memory");
-        wl_mma16(acc, buf, ca, cb);
+        wl_mma<KC>(acc, buf, ca, cb);
         if (c + 2 < nch) {
             // every read of this buffer has returned before it is refilled
             __builtin_amdgcn_s_waitcnt(WL_LGKM0);
             __builtin_amdgcn_wave_barrier();
             asm volatile("" ::: "memory");
-            wl_issue<CA, CB>(sg, ca, cb, avalid, k0 + 16 * (c + 2), buf);
+            wl_issue<KC, CA, CB>(sg, ca, cb, avalid, k0 + KC * (c + 2), buf);
         }
     }
     __builtin_amdgcn_s_waitcnt(WL_LGKM0);
     __builtin_amdgcn_wave_barrier();
 }
 
+template <int KC>
 __device__ inline void wave_seg(dbl4 (&acc)[2][2], const Seg& sg, int k0, int k1, double* sw) {
     const int c = __builtin_amdgcn_readfirstlane((sg.ca ? 1 : 0) | (sg.cb ? 2 : 0));
-    if (c == 1) wave_seg_t<1, 0>(acc, sg, k0, k1, sw);
-    else if (c == 2) wave_seg_t<0, 1>(acc, sg, k0, k1, sw);
-    else if (c == 3) wave_seg_t<1, 1>(acc, sg, k0, k1, sw);
-    else wave_seg_t<0, 0>(acc, sg, k0, k1, sw);
+    if (c == 1) wave_seg_t<KC, 1, 0>(acc, sg, k0, k1, sw);
+    else if (c == 2) wave_seg_t<KC, 0, 1>(acc, sg, k0, k1, sw);
+    else if (c == 3) wave_seg_t<KC, 1, 1>(acc, sg, k0, k1, sw);
+    else wave_seg_t<KC, 0, 0>(acc, sg, k0, k1, sw);
 }
 
 // Run this wavefront's share of a reduction made of nseg segments of total
 // length ktot (a multiple of 16); seg(q) returns segment q.  The reduction is
 // cut at multiples of 16 into four consecutive pieces, one per wavefront.
-// smem: WS_SMEM_DOUBLES doubles.
+// smem: WS<KC>::SMEM doubles.
 // Only the range [kbeg, kend) of the reduction is done when kend >= 0
 // (multiples of 16).
-template <class F>
+template <int KC, class F>
 __device__ inline void wave_segs(dbl4 (&acc)[2][2], int nseg, int ktot, double* smem, F&& seg, int kbeg = 0,
                                  int kend = -1) {
     if (kend < 0) kend = ktot;
@@ -200,13 +219,13 @@ __device__ inline void wave_segs(dbl4 (&acc)[2][2], int nseg, int ktot, double* 
     int kb = kbeg + 16 * per * w, ke = kbeg + 16 * per * (w + 1);
     if (ke > kend) ke = kend;
     if (kb > kend) kb = kend;
-    double* sw = smem + w * WS_WAVE_DOUBLES;
+    double* sw = smem + w * WS<KC>::WAVE;
     int s0 = 0;
     for (int q = 0; q < nseg && s0 < ke; ++q) {
         const Seg sg = seg(q);
         const int lo = kb > s0 ? kb : s0;
         const int hi = ke < s0 + sg.K ? ke : s0 + sg.K;
-        if (lo < hi) wave_seg(acc, sg, lo - s0, hi - s0, sw);
+        if (lo < hi) wave_seg<KC>(acc, sg, lo - s0, hi - s0, sw);
         s0 += sg.K;
     }
 }
@@ -215,8 +234,9 @@ __device__ inline void wave_segs(dbl4 (&acc)[2][2], int nseg, int ktot, double* 
 #define WR_SMEM_DOUBLES (4 * 32 * WR_LD)
 
 // Sum the four wavefronts' accumulators (wave 0 + 1 + 2 + 3, in that order)
-// into red[j*WR_LD + i] (column-major 32 x 32).  smem may be the staging area
-// of wave_segs (WS_SMEM_DOUBLES >= WR_SMEM_DOUBLES).  Ends with a barrier.
+// into red[j*WR_LD + i] (column-major 32 x 32).  smem (WR_SMEM_DOUBLES
+// doubles, which may be the staging area of wave_segs) must not overlap red.
+// Ends with a barrier.
 __device__ inline void wave_reduce(const dbl4 (&acc)[2][2], double* smem, double* red) {
     const int l = threadIdx.x & 63, w = threadIdx.x >> 6;
     __syncthreads();
