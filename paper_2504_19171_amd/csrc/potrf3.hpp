@@ -5,10 +5,10 @@
 //     panel; the reduced current panel sits in LDS in transposed MFMA form
 //     (lane (i, k) reads C[16I + i][c0 + 4r + k], the layout the matrix cores
 //     take as the B operand, so the panel solve needs no shuffle);
-//   - the diagonal 16 x 16 block is factored by wavefront 0 (two 8 x 8
-//     Cholesky factorizations and inverses kept in registers, redundantly in
-//     every lane, joined by an 8 x 8 TRSM and SYRK), while the other
-//     wavefronts reduce the panels ahead of it (see potrf3 below);
+//   - the diagonal 16 x 16 block is factored by wavefront 0 (one column per
+//     lane, pivot columns broadcast along 16-lane rows with DPP, the inverse
+//     formed in the same sweep; see p3_factor16), while the other wavefronts
+//     reduce the panels ahead of it (see potrf3 below);
 //   - the panel below is solved with the inverse of the diagonal block on the
 //     matrix cores, L_Ip^T = Y_pp C_Ip^T.
 // Also returns the inverses of the 16 x 16 diagonal blocks of L (for the
@@ -26,10 +26,9 @@
 
 struct P3Smem {
     double D[16 * P3_LD];          // diagonal block of the current panel, D(i, j) at D[j * P3_LD + i]
+                                   // (both triangles on input to p3_factor16, L_pp in the lower one after)
     double Y[2][16 * P3_LD];       // Y_p = L_pp^{-1} in Y[p & 1], Y(i, j) at [i * P3_LD + j]: the panel
                                    // wavefronts still read Y_p while wavefront 0 forms Y_{p+1}
-    double S22[8 * 9];             // factor16 scratch: S(i, j) at S22[i * 9 + j]
-    double T[8 * 9];               // T = L21 Y11, T(i, j) at T[i * 9 + j]
     double Dn[2][16 * P3_LD];      // next diagonal blocks (by parity), reduced up to two panels back
     double pool[P3_POOL][256];     // tiles (I, k) of L in slots given by p3_slot: first the reduced tile in
                                    // transposed MFMA form (r * 64 + lane), then, solved in place,
@@ -39,9 +38,6 @@ struct P3Smem {
     double lsum, lcomp;
     int fail;
 };
-
-// Packed lower triangle of an 8 x 8 matrix, by columns.
-#define P8(i, j) ((j) * 8 - ((j) * ((j) - 1)) / 2 + ((i) - (j)))
 
 // sqrt(x) and 1/sqrt(x) from the hardware reciprocal square root and two
 // Goldschmidt steps (a few ulp; the pivot decides nothing else).
@@ -58,44 +54,6 @@ __device__ inline void p3_sqrt_rsqrt(double x, double& s, double& r) {
     r = 2.0 * h;
 }
 
-// In-register Cholesky of the packed 8 x 8 lower triangle a; rinv[j] = 1/L_jj.
-// (The logarithms of the pivots are taken after the sweep, off this chain.)
-// *fail gets the first local column (base + j) whose pivot is not positive.
-__device__ inline void p3_chol8(double (&a)[36], double (&rinv)[8], int base, int& fail) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-        const double piv = a[P8(j, j)];
-        if (!(piv > 0.0) && fail < 0) fail = base + j;
-        double s, r;
-        p3_sqrt_rsqrt(piv, s, r);
-        a[P8(j, j)] = s;
-        rinv[j] = r;
-#pragma unroll
-        for (int i = j + 1; i < 8; ++i) a[P8(i, j)] *= r;
-#pragma unroll
-        for (int k = j + 1; k < 8; ++k)
-#pragma unroll
-            for (int i = k; i < 8; ++i) a[P8(i, k)] = fma(-a[P8(i, j)], a[P8(k, j)], a[P8(i, k)]);
-    }
-}
-
-// In place: the packed 8 x 8 lower-triangular L becomes L^{-1} (rinv = 1/L_jj).
-// Column j is done top down; y_ij needs L_ik (k >= j, columns not yet
-// replaced, and L_ij itself still in place) and y_kj (k < i, already there).
-__device__ inline void p3_inv8(double (&a)[36], const double (&rinv)[8]) {
-#pragma unroll
-    for (int j = 0; j < 8; ++j) {
-#pragma unroll
-        for (int i = j + 1; i < 8; ++i) {
-            double s = a[P8(i, j)] * rinv[j];
-#pragma unroll
-            for (int k = j + 1; k < i; ++k) s = fma(a[P8(i, k)], a[P8(k, j)], s);
-            a[P8(i, j)] = -s * rinv[i];
-        }
-        a[P8(j, j)] = rinv[j];
-    }
-}
-
 // Workgroup barriers: LDS traffic only (the phases exchange data through LDS
 // alone), or also every global access of every wavefront (before a panel is
 // announced).  The "memory" clobber keeps the compiler from moving accesses
@@ -109,98 +67,101 @@ __device__ inline void p3_wsync() {
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Store a packed 8 x 8 lower triangle (identical in every lane) into LDS
-// from lane 0, at compile-time addresses.  ToY: into Y ([row][col]) at
-// block offset o; otherwise into sm.D ([col][row]), the diagonal also into
-// sm.dg.
-template <bool ToY>
-__device__ inline void p3_put8(P3Smem& sm, double* Y, const double (&l)[36], int o, int base) {
-    if ((threadIdx.x & 63) != 0) return;
-#pragma unroll
-    for (int jj = 0; jj < 8; ++jj)
-#pragma unroll
-        for (int ii = jj; ii < 8; ++ii) {
-            const int e = P8(ii, jj);
-            if (ToY) {
-                Y[(o + ii) * P3_LD + o + jj] = l[e];
-            } else {
-                sm.D[(o + jj) * P3_LD + o + ii] = l[e];
-                if (ii == jj) sm.dg[base + o + ii] = l[e];
-            }
-        }
+// Value of lane K of this lane's 16-lane row (DPP row_newbcast:K).
+template <int K>
+__device__ __forceinline__ double p3_rowbcast(double v) {
+    return __builtin_amdgcn_mov_dpp(v, 0x150 + K, 0xF, 0xF, true);
+}
+// The same for a lane index known at compile time after unrolling.
+__device__ __forceinline__ double p3_rowbcast_i(double v, int i) {
+    switch (i) {
+    case 0: return p3_rowbcast<0>(v);
+    case 1: return p3_rowbcast<1>(v);
+    case 2: return p3_rowbcast<2>(v);
+    case 3: return p3_rowbcast<3>(v);
+    case 4: return p3_rowbcast<4>(v);
+    case 5: return p3_rowbcast<5>(v);
+    case 6: return p3_rowbcast<6>(v);
+    case 7: return p3_rowbcast<7>(v);
+    case 8: return p3_rowbcast<8>(v);
+    case 9: return p3_rowbcast<9>(v);
+    case 10: return p3_rowbcast<10>(v);
+    case 11: return p3_rowbcast<11>(v);
+    case 12: return p3_rowbcast<12>(v);
+    case 13: return p3_rowbcast<13>(v);
+    case 14: return p3_rowbcast<14>(v);
+    default: return p3_rowbcast<15>(v);
+    }
 }
 
-// Factor the 16 x 16 block in sm.D (lower part) on one wavefront: L_pp back
-// into the lower part of sm.D ([col][row]; the upper part is left as is) and
-// Y = L_pp^{-1} into the lower part of Y ([row][col]; its upper part is
-// zero from the start).  With D = [D11 .; D21 D22] (8 x 8 blocks):
-// L11 = chol(D11), L21 = D21 L11^{-T} (row by row), S = D22 - L21 L21^T,
-// L22 = chol(S), and Y = [Y11 0; -Y22 L21 Y11  Y22].
+// Pivot K of the sweep in p3_factor16.  Lane j of every 16-lane row holds a
+// column x of 16 values.  Before pivot K:
+//   - a lane with j >= K holds column j of the partly reduced block A^(K)
+//     (rows >= K; rows < K were cleared as they were used);
+//   - a lane with j < K holds, in the rows whose role is the inverse (wrow),
+//     Z = -d_j times column j of W^(K) = E_{K-1} ... E_0 (E_k: the k-th
+//     elimination step, so W^(16) = U^{-1} for A = U diag(d) U^T, U unit lower
+//     triangular), and in the other rows column j of U diag(d), kept.
+// The step: d = A^(K)(K, K) from lane K; every lane forms q = x_K / d (for
+// j > K the multiplier A^(K)(K, j) / d by symmetry; for j < K the entry
+// W(K, j) scaled as above) and adds -A^(K)(i, K) q to its rows i > K, the
+// pivot column A^(K)(i, K) coming from lane K.  Lane K itself changes no row
+// below K: its column is U(:, K) d_K, which is also -d_K times column K of
+// W^(K+1) below the diagonal, so only its diagonal entry becomes -d_K.
+template <int K>
+__device__ __forceinline__ void p3_pivot(double (&x)[16], double& dj, int& fail, int base, int j, bool wrow) {
+    const double d = p3_rowbcast<K>(x[K]);
+    double rr = __builtin_amdgcn_rcp(d);   // 1/d: hardware estimate and two Newton steps
+    double e = fma(-d, rr, 1.0);
+    rr = fma(rr, e, rr);
+    e = fma(-d, rr, 1.0);
+    rr = fma(rr, e, rr);
+    if (!(d > 0.0) && fail < 0) fail = base + K;
+    const double q = x[K] * rr;
+    const double c = (j != K && (wrow || j > K)) ? q : 0.0;
+    dj = (j == K) ? d : dj;
+    x[K] = (j < K) ? x[K] : ((j == K) ? -x[K] : 0.0);
+#pragma unroll
+    for (int i = K + 1; i < 16; ++i) x[i] = fma(-p3_rowbcast<K>(x[i]), c, x[i]);
+}
+template <int K>
+__device__ __forceinline__ void p3_pivots(double (&x)[16], double& dj, int& fail, int base, int j, bool wrow) {
+    p3_pivot<K>(x, dj, fail, base, j, wrow);
+    if constexpr (K < 15) p3_pivots<K + 1>(x, dj, fail, base, j, wrow);
+}
+
+// Factor the 16 x 16 block in sm.D (both triangles, symmetric) on one
+// wavefront: L_pp into the lower part of sm.D ([col][row]; the upper part is
+// overwritten with zeros), its diagonal into sm.dg, and Y = L_pp^{-1} into all
+// of Y ([row][col], zeros above the diagonal).  A = U diag(d) U^T by the
+// pivots of p3_pivot, each lane keeping one column, each pivot column
+// broadcast along the lane rows (no LDS traffic inside the sweep); then
+// L = U diag(d)^{1/2} and Y = diag(d)^{-1/2} U^{-1}, so
+//   L(i, j) = [U diag(d)](i, j) / sqrt(d_j),   Y(i, j) = -Z(i, j) / (sqrt(d_i) d_j).
+// Rows 0 and 2 of the wavefront carry the inverse, rows 1 and 3 the factor.
+// *fail gets the first local column (base + j) whose pivot is not positive.
 __device__ inline void p3_factor16(P3Smem& sm, double* Y, int base, int& fail) {
-    const int lane = threadIdx.x & 63;
-    double a[36], r[8], l21[8];
-    // 1. L11 = chol(D11), in every lane; lane i < 8 forms row i of L21 (in place in sm.D)
+    const int lane = threadIdx.x & 63, j = lane & 15;
+    const bool wrow = (lane & 16) == 0;
+    double x[16];
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
+    for (int i = 0; i < 16; ++i) x[i] = sm.D[j * P3_LD + i];
+    double dj = 1.0;
+    p3_pivots<0>(x, dj, fail, base, j, wrow);
+    double s, r;   // sqrt(d_j), 1/sqrt(d_j)
+    p3_sqrt_rsqrt(dj, s, r);
+    const double f = -(r * r);
+    double g[16];   // -1/(sqrt(d_i) d_j)
 #pragma unroll
-        for (int i = j; i < 8; ++i) a[P8(i, j)] = sm.D[j * P3_LD + i];
-    p3_chol8(a, r, base, fail);
-    if (lane < 8) {
+    for (int i = 0; i < 16; ++i) g[i] = p3_rowbcast_i(r, i) * f;
+    if (lane < 16) {
 #pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            double v = sm.D[j * P3_LD + 8 + lane];
+        for (int i = 0; i < 16; ++i) Y[i * P3_LD + j] = x[i] * g[i];
+    } else if (lane < 32) {
 #pragma unroll
-            for (int k = 0; k < j; ++k) v = fma(-l21[k], a[P8(j, k)], v);
-            l21[j] = v * r[j];
-            sm.D[j * P3_LD + 8 + lane] = l21[j];
-        }
-    }
-    // 2. Y11 = L11^{-1} (in place); T = L21 Y11 (row i on lane i < 8)
-    p3_put8<false>(sm, Y, a, 0, base);
-    p3_inv8(a, r);
-    p3_put8<true>(sm, Y, a, 0, base);
-    if (lane < 8) {
-#pragma unroll
-        for (int j = 0; j < 8; ++j) {
-            double v = 0.0;
-#pragma unroll
-            for (int k = j; k < 8; ++k) v = fma(l21[k], a[P8(k, j)], v);
-            sm.T[lane * 9 + j] = v;
-        }
-    }
-    p3_wsync();
-    // 3. S = D22 - L21 L21^T, lane (i, j), j <= i
-    {
-        const int i = lane >> 3, jj = lane & 7;
-        if (jj <= i) {
-            double v = sm.D[(8 + jj) * P3_LD + 8 + i];
-#pragma unroll
-            for (int k = 0; k < 8; ++k) v = fma(-sm.D[k * P3_LD + 8 + i], sm.D[k * P3_LD + 8 + jj], v);
-            sm.S22[i * 9 + jj] = v;
-        }
-    }
-    p3_wsync();
-    // 4. L22 = chol(S), Y22 = L22^{-1}, in every lane
-#pragma unroll
-    for (int j = 0; j < 8; ++j)
-#pragma unroll
-        for (int i = j; i < 8; ++i) a[P8(i, j)] = sm.S22[i * 9 + j];
-    p3_chol8(a, r, base + 8, fail);
-    p3_put8<false>(sm, Y, a, 8, base);
-    p3_inv8(a, r);
-    p3_put8<true>(sm, Y, a, 8, base);
-    // 5. Y21 = -Y22 T, column j on lane j < 8
-    if (lane < 8) {
-        double t[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) t[k] = sm.T[k * 9 + lane];
-#pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            double v = 0.0;
-#pragma unroll
-            for (int k = 0; k <= i; ++k) v = fma(a[P8(i, k)], t[k], v);
-            Y[(8 + i) * P3_LD + lane] = -v;
-        }
+        for (int i = 0; i < 16; ++i) sm.D[j * P3_LD + i] = x[i] * r;
+        sm.D[j * P3_LD + j] = s;
+        sm.dg[base + j] = s;
     }
 }
 
@@ -466,8 +427,9 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
 #pragma unroll
         for (int I = 1; I < 16; ++I)
             if (I < np) sm.pool[p3_slot(tab, I, 0)][q] = v[I];
+        // D_0 symmetric from the lower triangle of the tile
         const int i = threadIdx.x & 15, j = threadIdx.x >> 4;
-        sm.D[j * P3_LD + i] = ld_coh_s(Mc, (uint32_t)(i + j * ldi));
+        sm.D[j * P3_LD + i] = ld_coh_s(Mc, (uint32_t)(imax_(i, j) + imin_(i, j) * ldi));
     }
     for (int e = threadIdx.x; e < 2 * 16 * P3_LD; e += 256) sm.Y[0][e] = 0.0;
     // panel wavefronts w = 1..P3_PW own the row tiles I = P3_PW s + w >= 1 of every panel
@@ -530,6 +492,10 @@ __device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& 
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) sm.D[(4 * r + lk) * P3_LD + li] = acc[r];
+            // the upper triangle mirrored from the lower one (p3_factor16 reads both)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                if (li > 4 * r + lk) sm.D[li * P3_LD + 4 * r + lk] = acc[r];
             p3_wsync();
             p3_factor16(sm, sm.Y[(p + 1) & 1], c0 + 16, fail);
         } else if (p + 2 < np) {
