@@ -615,10 +615,17 @@ def leg_served(njobs, tile=0, budget_gb=64.0, lanes=3, max_batch=8, fracs=(0.5, 
                 out = serve.serve_plain(jobs, tile)
             lat = np.array([j.done - j.arrival for j in out]) * 1e3
             span = max(j.done for j in out) - min(j.arrival for j in out)
-            ok &= all(j.info == (0, 0) and np.isfinite(j.logdet) for j in out)
+            bad = [j for j in out if not (j.info == (0, 0) and np.isfinite(j.logdet))]
+            ok &= not bad
             res[form] = {"latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
                          "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
                          "solves_per_s": round(len(out) / span, 3)}
+            if bad:
+                # which jobs failed, with their (factor, selinv) status codes
+                res[form]["failed"] = len(bad)
+                res[form]["failed_jobs"] = [
+                    {"job": j.jid, "nb": j.nb, "w": j.w, "a": j.a, "info": list(j.info),
+                     "latency_ms": round((j.done - j.arrival) * 1e3, 3)} for j in bad[:10]]
             if form == "served":
                 res[form]["peak_bytes_held"] = srv.peak
             for j in jobs:
@@ -635,7 +642,8 @@ def leg_served(njobs, tile=0, budget_gb=64.0, lanes=3, max_batch=8, fracs=(0.5, 
 def main_served(args) -> int:
     r = leg_served(args.jobs, tile=args.tile, budget_gb=args.budget_gb, lanes=args.lanes,
                    max_batch=args.max_batch, fracs=tuple(float(x) for x in args.fracs.split(",")), log=_log)
-    top = r["rates"]["0.8"]["served"]
+    # the headline rate: 0.8 x capacity when it was run, else the highest rate run
+    top = r["rates"]["0.8" if "0.8" in r["rates"] else max(r["rates"], key=float)]["served"]
     out = {
         "metric": METRIC,
         "value": top["solves_per_s"],

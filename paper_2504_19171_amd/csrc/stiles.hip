@@ -1084,16 +1084,18 @@ __device__ inline void p2_dep_offdiag(const P2& p, SchedDeps& d, int64_t J) {
 
 // LDS of a Phase 2 workgroup: the wavefronts' staging areas, which
 // wave_reduce reuses for the partial blocks (the larger of the two), then the
-// reduced block.  The single-matrix kernel, bound by its dependency chain,
-// runs two workgroups per CU with 16-deep chunks; the batched one, which has
-// the independent work of many matrices to overlap, three with 8-deep chunks
-// (measured: 125 against 140 ms per batched pass; the single matrix's Phase
-// 2 took 23 ms instead of 17 that way).
+// reduced block.  Both kernels run two workgroups per CU.  The single-matrix
+// kernel stages 16-deep chunks; the batched one 8-deep chunks, which halve its
+// LDS (41 against 72 KB), so that the kernels of other serving lanes still
+// find room on a CU beside it.  (Three batched workgroups per CU, which the
+// 8-deep chunks allow, made a batched pass faster alone, 125 against 141 ms,
+// but filled every CU: concurrent serving lanes then lost capacity, and in the
+// 2,000-job served stream one batch's selected inverse hit the wait limit.)
 template <int KC>
 struct P2Cfg {
     static constexpr int STAGE = WS<KC>::SMEM > WR_SMEM_DOUBLES ? WS<KC>::SMEM : WR_SMEM_DOUBLES;
     static constexpr int SMEM = STAGE + 32 * WR_LD;
-    static constexpr int WG_PER_CU = KC == 16 ? 2 : 3;
+    static constexpr int WG_PER_CU = 2;
 };
 #define P2_KC_SINGLE 16
 #define P2_KC_BATCHED 8
@@ -2312,6 +2314,60 @@ size_t stiles_batch_workspace_bytes(const stiles_batch_item* items, int32_t coun
 
 // Host side of both batched calls: the matrix table (and the segment tables
 // appended to `segs`) go to the table area of the workspace in one copy.
+// Pinned host buffers for the table uploads, kept for the life of the
+// process.  A buffer is handed out again only once the event recorded after
+// its copy has completed, so calls on several streams at once (concurrent
+// serving lanes) never overwrite a table that is still being copied.
+struct PinnedBuf {
+    char* p;
+    size_t cap;
+    hipEvent_t done;
+};
+static std::mutex g_pmu;
+static std::vector<PinnedBuf> g_pin;
+#define PIN_MAX_BUFS 16
+
+// Host bytes -> device, through a pinned buffer, on stream st.
+static int pinned_upload(void* dst, const void* src, size_t n, hipStream_t st) {
+    std::lock_guard<std::mutex> lk(g_pmu);
+    PinnedBuf* b = nullptr;
+    for (auto& x : g_pin)
+        if (x.cap >= n && hipEventQuery(x.done) == hipSuccess) {
+            b = &x;
+            break;
+        }
+    if (!b && g_pin.size() < PIN_MAX_BUFS) {
+        PinnedBuf x;
+        x.cap = std::max<size_t>(n, 1 << 16);
+        HIPCHK(hipHostMalloc((void**)&x.p, x.cap, hipHostMallocDefault));
+        if (hipEventCreateWithFlags(&x.done, hipEventDisableTiming) != hipSuccess) {
+            (void)hipHostFree(x.p);
+            return STILES_EHIP;
+        }
+        g_pin.push_back(x);
+        b = &g_pin.back();
+    }
+    if (!b) {
+        // every buffer busy: wait for the first one large enough, else grow it
+        b = &g_pin[0];
+        for (auto& x : g_pin)
+            if (x.cap >= n) {
+                b = &x;
+                break;
+            }
+        HIPCHK(hipEventSynchronize(b->done));
+        if (b->cap < n) {
+            HIPCHK(hipHostFree(b->p));
+            b->cap = n;
+            HIPCHK(hipHostMalloc((void**)&b->p, b->cap, hipHostMallocDefault));
+        }
+    }
+    memcpy(b->p, src, n);
+    HIPCHK(hipMemcpyAsync(dst, b->p, n, hipMemcpyHostToDevice, st));
+    HIPCHK(hipEventRecord(b->done, st));
+    return 0;
+}
+
 static int batch_upload(const std::vector<BInst>& bi, const std::vector<BSeg>& segs, const std::vector<int>& idx,
                         char* ws, hipStream_t st) {
     const size_t o1 = align256(sizeof(BInst) * bi.size()), o2 = o1 + align256(sizeof(BSeg) * 6 * (bi.size() + 1));
@@ -2319,9 +2375,7 @@ static int batch_upload(const std::vector<BInst>& bi, const std::vector<BSeg>& s
     memcpy(h.data(), bi.data(), sizeof(BInst) * bi.size());
     memcpy(h.data() + o1, segs.data(), sizeof(BSeg) * segs.size());
     if (!idx.empty()) memcpy(h.data() + o2, idx.data(), sizeof(int) * idx.size());
-    // from pageable memory: the data are staged before the call returns
-    HIPCHK(hipMemcpyAsync(ws, h.data(), h.size(), hipMemcpyHostToDevice, st));
-    return 0;
+    return pinned_upload(ws, h.data(), h.size(), st);
 }
 
 // What a batched call does: upload its tables (host -> workspace, a copy
