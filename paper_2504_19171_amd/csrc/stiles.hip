@@ -97,6 +97,7 @@ __global__ void k_set_int(int* p, int v) {
 #define PACK_CB 32
 #define PACK_RB 256
 #define PACK_SMEM_DOUBLES (PACK_CB * (PACK_RB + 1))
+#define PACK_U 8   // loads in flight per thread
 __global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, const double* __restrict__ P,
                                             const double* __restrict__ C, double* __restrict__ T, Lay L) {
     __shared__ double blk[PACK_SMEM_DOUBLES];   // [c][r]: column c at c * b (band) or c * (rows + 1) (arrow)
@@ -114,20 +115,26 @@ __global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, cons
             // 64 x 64 tiles: the staging costs more than it saves (each block
             // would read 95 band-form rows for 64 tile rows); thread t writes
             // row t % 64 of columns t / 64, t / 64 + 4, ...
+            // (every load from a valid address, the unused ones dropped: a
+            // load under a branch would wait before the next one issues)
             const int r = tid % 64;
             const int64_t i = i0 + r;
-            for (int c = tid / 64; c < 64; c += NT / 64) {
+            constexpr int NQ = 64 / (NT / 64);
+            double v[NQ];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int64_t j = j0 + tid / 64 + q * (NT / 64);
+                const int64_t k = i >= j ? i - j : j - i, lo = i >= j ? j : i;
+                const bool ok = live && i < L.nb && j < L.nb && k <= L.w;
+                v[q] = ab[ok ? k * L.nb + lo : 0];
+            }
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                const int c = tid / 64 + q * (NT / 64);
                 const int64_t j = j0 + c;
-                double v = 0.0;
-                if (live) {
-                    if (i < L.nb && j < L.nb) {
-                        const int64_t k = i >= j ? i - j : j - i, lo = i >= j ? j : i;
-                        if (k <= L.w) v = ab[k * L.nb + lo];
-                    } else if (i == j) {
-                        v = 1.0;
-                    }
-                }
-                O[r + c * 64] = v;
+                const bool in = live && i < L.nb && j < L.nb;
+                const int64_t k = i >= j ? i - j : j - i;
+                O[r + c * 64] = (in && k <= L.w) ? v[q] : ((live && !in && i == j) ? 1.0 : 0.0);
             }
             return;
         }
@@ -139,25 +146,48 @@ __global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, cons
             }
             __syncthreads();
             if (live) {
-                // on and below the diagonal: k = d b + r - c', c' = cb + c
+                // on and below the diagonal: k = d b + r - c', c' = cb + c.
+                // PACK_U loads per thread are issued before their LDS stores,
+                // each from a valid address (the unused ones dropped): a load
+                // under a branch would wait before the next one issues.
                 const int klo = imax_(0, d * b - cb - (PACK_CB - 1)), khi = imin_((int)L.w, d * b + b - 1 - cb);
                 const int n = (khi - klo + 1) * PACK_CB;
-#pragma unroll 4
-                for (int e = tid; e < n; e += NT) {
-                    const int k = klo + e / PACK_CB, c = e % PACK_CB;
-                    const int r = k - d * b + cb + c;
-                    const int64_t j = j0 + cb + c;
-                    if (r >= 0 && r < b && i0 + r < L.nb && j < L.nb) blk[c * b + r] = ab[(int64_t)k * L.nb + j];
+                for (int e0 = tid; e0 < n; e0 += NT * PACK_U) {
+                    double v[PACK_U];
+                    int at[PACK_U];
+#pragma unroll
+                    for (int q = 0; q < PACK_U; ++q) {
+                        const int e = e0 + q * NT;
+                        const int k = klo + e / PACK_CB, c = e % PACK_CB;
+                        const int r = k - d * b + cb + c;
+                        const int64_t j = j0 + cb + c;
+                        const bool ok = e < n && r >= 0 && r < b && i0 + r < L.nb && j < L.nb;
+                        v[q] = ab[ok ? (int64_t)k * L.nb + j : 0];
+                        at[q] = ok ? c * b + r : -1;
+                    }
+#pragma unroll
+                    for (int q = 0; q < PACK_U; ++q)
+                        if (at[q] >= 0) blk[at[q]] = v[q];
                 }
                 if (d == 0) {
                     // above the diagonal: k = c' - r >= 1, value ab[k, j0 + r]
                     const int khi2 = imin_((int)L.w, cb + PACK_CB - 1);
                     const int n2 = imax_(khi2, 0) * PACK_CB;
-#pragma unroll 4
-                    for (int e = tid; e < n2; e += NT) {
-                        const int k = 1 + e / PACK_CB, c = e % PACK_CB;
-                        const int r = cb + c - k;
-                        if (r >= 0 && j0 + cb + c < L.nb) blk[c * b + r] = ab[(int64_t)k * L.nb + j0 + r];
+                    for (int e0 = tid; e0 < n2; e0 += NT * PACK_U) {
+                        double v[PACK_U];
+                        int at[PACK_U];
+#pragma unroll
+                        for (int q = 0; q < PACK_U; ++q) {
+                            const int e = e0 + q * NT;
+                            const int k = 1 + e / PACK_CB, c = e % PACK_CB;
+                            const int r = cb + c - k;
+                            const bool ok = e < n2 && r >= 0 && j0 + cb + c < L.nb;
+                            v[q] = ab[ok ? (int64_t)k * L.nb + j0 + r : 0];
+                            at[q] = ok ? c * b + r : -1;
+                        }
+#pragma unroll
+                        for (int q = 0; q < PACK_U; ++q)
+                            if (at[q] >= 0) blk[at[q]] = v[q];
                     }
                 }
             }
@@ -174,10 +204,22 @@ __global__ __launch_bounds__(NT) void k_pack(const double* __restrict__ ab, cons
             for (int rb = 0; rb < ap; rb += PACK_RB) {
                 const int nr = imin_(PACK_RB, ap - rb);
                 // rows r of P over the block's 32 columns (contiguous), into [c][r]
-                for (int e = tid; e < nr * PACK_CB; e += NT) {
-                    const int r = e / PACK_CB, c = e % PACK_CB;
-                    const int64_t j = j0 + cb + c;
-                    blk[c * (nr + 1) + r] = (rb + r < L.a && j < L.nb) ? P[(int64_t)(rb + r) * L.nb + j] : 0.0;
+                for (int e0 = tid; e0 < nr * PACK_CB; e0 += NT * PACK_U) {
+                    double v[PACK_U];
+                    int at[PACK_U];
+                    bool ok[PACK_U];
+#pragma unroll
+                    for (int q = 0; q < PACK_U; ++q) {
+                        const int e = e0 + q * NT;
+                        const int r = e / PACK_CB, c = e % PACK_CB;
+                        const int64_t j = j0 + cb + c;
+                        ok[q] = rb + r < L.a && j < L.nb;
+                        v[q] = P[ok[q] ? (int64_t)(rb + r) * L.nb + j : 0];
+                        at[q] = e < nr * PACK_CB ? c * (nr + 1) + r : -1;
+                    }
+#pragma unroll
+                    for (int q = 0; q < PACK_U; ++q)
+                        if (at[q] >= 0) blk[at[q]] = ok[q] ? v[q] : 0.0;
                 }
                 __syncthreads();
                 for (int e = tid; e < nr * PACK_CB; e += NT) {
