@@ -21,16 +21,18 @@ def _events():
     return torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
 
 
-def batch_buffers(mats, shapes, tile):
+def batch_buffers(mats, shapes, tile, in_place: bool = False):
     """Layouts, packed inputs and output buffers of a batch at one tile size.
 
     mats: [(ab, P, C)] device tensors (canonical band form, P and C None
-    without an arrow); shapes: [(n, w, a)]."""
+    without an arrow); shapes: [(n, w, a)].  in_place: each matrix is packed
+    straight into its L buffer and factored there (the As are the Ls), as the
+    single-matrix step does; otherwise the factor first copies A into L."""
     import torch
     lays = [st.layout(n, w, a, tile) for (n, w, a) in shapes]
     As = [st.pack(ab, P, C, lay) for (ab, P, C), lay in zip(mats, lays)]
     dev = As[0].device
-    Ls = [torch.empty_like(x) for x in As]
+    Ls = As if in_place else [torch.empty_like(x) for x in As]
     Ss = [torch.empty_like(x) for x in As]
     ws = torch.empty(st.batch_workspace_bytes(lays), dtype=torch.uint8, device=dev)
     return dict(lays=lays, As=As, Ls=Ls, Ss=Ss, ws=ws, tile=tile)
@@ -79,9 +81,10 @@ def capture_batched(buf):
 
 
 def time_batched(mats, shapes, tile, reps: int = 1) -> Tuple[float, dict]:
-    """Milliseconds of one batched pass at this tile size (after one untimed pass)."""
+    """Milliseconds of one batched pass at this tile size (after one untimed pass);
+    each matrix is packed into its L and factored in place."""
     import torch
-    buf = batch_buffers(mats, shapes, tile)
+    buf = batch_buffers(mats, shapes, tile, in_place=True)
     buf["mats"] = mats
     run_batched(buf)
     torch.cuda.synchronize()
@@ -95,20 +98,20 @@ def time_batched(mats, shapes, tile, reps: int = 1) -> Tuple[float, dict]:
 
 
 def time_plain(mats, shapes, tile) -> List[float]:
-    """Milliseconds of pack + factor + selinv of each matrix alone (its own launches)."""
+    """Milliseconds of pack + factor + selinv of each matrix alone (its own launches;
+    packed into L and factored in place, as in the batched pass)."""
     import torch
     out = []
     for (ab, P, C), (n, w, a) in zip(mats, shapes):
         lay = st.layout(n, w, a, tile)
-        A = torch.empty(lay.total_doubles, dtype=torch.float64, device=ab.device)
-        L = torch.empty_like(A)
-        S = torch.empty_like(A)
+        L = torch.empty(lay.total_doubles, dtype=torch.float64, device=ab.device)
+        S = torch.empty_like(L)
         wf = torch.empty(lay.factor_workspace_bytes, dtype=torch.uint8, device=ab.device)
         wsl = torch.empty(lay.selinv_workspace_bytes, dtype=torch.uint8, device=ab.device)
 
         def once():
-            st.pack(ab, P, C, lay, out=A)
-            st.factor(A, lay, out=L, workspace=wf)
+            st.pack(ab, P, C, lay, out=L)
+            st.factor(L, lay, out=L, workspace=wf)
             st.selinv(L, lay, out=S, workspace=wsl)
         once()
         torch.cuda.synchronize()
@@ -118,7 +121,7 @@ def time_plain(mats, shapes, tile) -> List[float]:
         e1.record()
         torch.cuda.synchronize()
         out.append(e0.elapsed_time(e1))
-        del A, L, S, wf, wsl
+        del L, S, wf, wsl
     return out
 
 

@@ -37,6 +37,17 @@ __host__ __device__ inline int imin_(int x, int y) { return x < y ? x : y; }
 __host__ __device__ inline int imax_(int x, int y) { return x > y ? x : y; }
 __host__ __device__ inline int64_t imax64(int64_t x, int64_t y) { return x > y ? x : y; }
 
+// The workgroups of a launch are dealt to the 8 XCDs in turn (workgroup i to
+// XCD i mod 8), and each XCD has its own L2.  xcd_block renumbers them so that
+// every XCD holds one contiguous run of logical blocks: neighbouring blocks,
+// which read the same operand strips, then share one L2 instead of fetching
+// the strip once per XCD.  A bijection on [0, G) for any G, so correctness
+// does not depend on the dealing order.
+__host__ __device__ inline int xcd_block(int b, int G) {
+    const int x = b & 7, slot = b >> 3, q = G >> 3, r = G & 7;
+    return x < r ? x * (q + 1) + slot : r * (q + 1) + (x - r) * q + slot;
+}
+
 // Global (device) memory address space.  Every pointer the kernels read or
 // write through is global memory, but a pointer the compiler cannot trace
 // back to a kernel argument (one rebuilt from an integer, say) is generic,

@@ -881,7 +881,8 @@ __device__ inline void trmm_body(const double* Lm, double* W, const Lay& L, int 
 __global__ __launch_bounds__(NT) void k_trmm_all(const double* Lm, double* W, Lay L, int64_t j0) {
     __shared__ double smem[GB_SMEM_DOUBLES];
     const int nb64 = L.b / 64;
-    trmm_body(Lm, W, L, (int)(blockIdx.x + j0 * (L.bt * nb64 + arrow_blocks(L.ap)) * nb64), smem);
+    trmm_body(Lm, W, L, xcd_block((int)blockIdx.x, (int)gridDim.x) + (int)(j0 * (L.bt * nb64 + arrow_blocks(L.ap)) * nb64),
+              smem);
 }
 
 // Phase 2 initial value of each diagonal tile, "LAUUM": Sigma_JJ = X_J^T X_J
@@ -921,7 +922,7 @@ __device__ inline void lauum_body(const double* W, double* S, const Lay& L, int 
 }
 __global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, Lay L, int64_t j0) {
     __shared__ double smem[GB_SMEM_DOUBLES];
-    lauum_body(W, S, L, (int)(blockIdx.x + j0 * lauum_per(L)), smem);
+    lauum_body(W, S, L, xcd_block((int)blockIdx.x, (int)gridDim.x) + (int)(j0 * lauum_per(L)), smem);
 }
 
 #define ARW (-1)   // "the arrow" in place of a band tile offset
@@ -1435,13 +1436,20 @@ __device__ inline int bseg_find(const BSeg* seg, int nseg, int b) {
     }
     return lo;
 }
-// this workgroup's matrix, index within the matrix's share, and share size
-#define BATCH_DECODE(a, I, bid, nblk)                                          \
-    const int q_ = bseg_find((a).seg, (a).nseg, (int)blockIdx.x);              \
+// the matrix of logical block B, B's index within the matrix's share, and
+// the share's size
+#define BATCH_DECODE_AT(a, I, bid, nblk, B)                                    \
+    const int b_ = (B);                                                        \
+    const int q_ = bseg_find((a).seg, (a).nseg, b_);                           \
     const BInst& I = (a).bi[(a).seg[q_].inst];                                 \
-    const int bid = (int)blockIdx.x - (a).seg[q_].first;                       \
+    const int bid = b_ - (a).seg[q_].first;                                    \
     const int nblk = (a).seg[q_ + 1].first - (a).seg[q_].first;                \
     (void)nblk
+// ... of this workgroup
+#define BATCH_DECODE(a, I, bid, nblk) BATCH_DECODE_AT(a, I, bid, nblk, (int)blockIdx.x)
+// ... of this workgroup's XCD-grouped number (blocks that share operands on one L2)
+#define BATCH_DECODE_XCD(a, I, bid, nblk) \
+    BATCH_DECODE_AT(a, I, bid, nblk, xcd_block((int)blockIdx.x, (int)gridDim.x))
 
 // Factor set-up of every matrix (one workgroup per matrix): info and error
 // words, tile column counters.
@@ -1540,13 +1548,13 @@ __global__ __launch_bounds__(NT) void kb_trtri(BArgs a) {
 
 __global__ __launch_bounds__(NT) void kb_trmm(BArgs a) {
     __shared__ double smem[GB_SMEM_DOUBLES];
-    BATCH_DECODE(a, I, bid, nblk);
+    BATCH_DECODE_XCD(a, I, bid, nblk);
     trmm_body(I.Lm, selinv_ws(I.L, I.ws).W, I.L, bid, smem);
 }
 
 __global__ __launch_bounds__(NT) void kb_lauum(BArgs a) {
     __shared__ double smem[GB_SMEM_DOUBLES];
-    BATCH_DECODE(a, I, bid, nblk);
+    BATCH_DECODE_XCD(a, I, bid, nblk);
     lauum_body(selinv_ws(I.L, I.ws).W, I.S, I.L, bid, smem);
 }
 
