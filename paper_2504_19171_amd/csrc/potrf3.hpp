@@ -22,15 +22,19 @@
 #define P3_PW 3                                    // panel wavefronts (1 .. P3_PW); wavefront 0 runs the diagonal chain
 #define P3_NT (64 * (1 + P3_PW))                   // threads of a workgroup running potrf3
 #define P3_SLOTS ((15 + P3_PW - 1) / P3_PW)        // row tiles I >= 1 per panel wavefront
-#define P3_POOL 65   // 16 x 16 tiles of L alive at once at m = 256 (checked by p3_make_slots)
+#define P3_POOL 65       // 16 x 16 tiles of L alive at once at m = 256 (checked by p3_make_slots)
+#define P3_POOL_128 17   // the same for m <= 128
 
-struct P3Smem {
+// NPOOL: pool slots, P3_POOL for any m, P3_POOL_128 for m <= 128 (a smaller
+// footprint lets more workgroups share a compute unit).
+template <int NPOOL>
+struct P3SmemT {
     double D[16 * P3_LD];          // diagonal block of the current panel, D(i, j) at D[j * P3_LD + i]
                                    // (both triangles on input to p3_factor16, L_pp in the lower one after)
     double Y[2][16 * P3_LD];       // Y_p = L_pp^{-1} in Y[p & 1], Y(i, j) at [i * P3_LD + j]: the panel
                                    // wavefronts still read Y_p while wavefront 0 forms Y_{p+1}
     double Dn[2][16 * P3_LD];      // next diagonal blocks (by parity), reduced up to two panels back
-    double pool[P3_POOL][256];     // tiles (I, k) of L in slots given by p3_slot: first the reduced tile in
+    double pool[NPOOL][256];       // tiles (I, k) of L in slots given by p3_slot: first the reduced tile in
                                    // transposed MFMA form (r * 64 + lane), then, solved in place,
                                    // L[16I + i][16k + j] at [j * 16 + i]
     double dg[256];                // diagonal of L, then 2 log L_jj
@@ -38,6 +42,7 @@ struct P3Smem {
     double lsum, lcomp;
     int fail;
 };
+using P3Smem = P3SmemT<P3_POOL>;
 
 // sqrt(x) and 1/sqrt(x) from the hardware reciprocal square root and two
 // Goldschmidt steps (a few ulp; the pivot decides nothing else).
@@ -140,7 +145,8 @@ __device__ __forceinline__ void p3_pivots(double (&x)[16], double& dj, int& fail
 //   L(i, j) = [U diag(d)](i, j) / sqrt(d_j),   Y(i, j) = -Z(i, j) / (sqrt(d_i) d_j).
 // Rows 0 and 2 of the wavefront carry the inverse, rows 1 and 3 the factor.
 // *fail gets the first local column (base + j) whose pivot is not positive.
-__device__ inline void p3_factor16(P3Smem& sm, double* Y, int base, int& fail) {
+template <int NPOOL>
+__device__ inline void p3_factor16(P3SmemT<NPOOL>& sm, double* Y, int base, int& fail) {
     const int lane = threadIdx.x & 63, j = lane & 15;
     const bool wrow = (lane & 16) == 0;
     double x[16];
@@ -175,6 +181,7 @@ __device__ inline void p3_factor16(P3Smem& sm, double* Y, int base, int& fail) {
 struct P3SlotPack {
     uint32_t w[4][64];
     int peak[4];
+    int top[4];   // largest slot index handed out
 };
 constexpr P3SlotPack p3_make_slots() {
     P3SlotPack t{};
@@ -185,10 +192,15 @@ constexpr P3SlotPack p3_make_slots() {
         int nf = 0, live = 0, peak = 0;
         for (int q = P3_POOL - 1; q >= 0; --q) fr[nf++] = q;
         // an empty free list makes fr[-1] below, which stops the compilation
-        for (int I = 1; I < np; ++I) { slot[I][0] = fr[--nf]; ++live; }
+        int top = 0;
+        for (int I = 1; I < np; ++I) { slot[I][0] = fr[--nf]; ++live; top = slot[I][0] > top ? slot[I][0] : top; }
         peak = live;
         for (int p = 0; p + 1 < np; ++p) {
-            for (int I = p + 2; I < np; ++I) { slot[I][p + 1] = fr[--nf]; ++live; }
+            for (int I = p + 2; I < np; ++I) {
+                slot[I][p + 1] = fr[--nf];
+                ++live;
+                top = slot[I][p + 1] > top ? slot[I][p + 1] : top;
+            }
             if (live > peak) peak = live;
             if (p + 2 < np)
                 for (int k = 0; k <= p; ++k) { fr[nf++] = slot[p + 2][k]; --live; }
@@ -198,11 +210,14 @@ constexpr P3SlotPack p3_make_slots() {
         for (int I = 0; I < 16; ++I)
             for (int k = 0; k < 16; ++k) t.w[v][16 * (I & 3) + k] |= (uint32_t)slot[I][k] << (8 * (I >> 2));
         t.peak[v] = peak;
+        t.top[v] = top;
     }
     return t;
 }
 constexpr P3SlotPack kP3Slots = p3_make_slots();
 static_assert(kP3Slots.peak[3] == P3_POOL && kP3Slots.peak[2] <= P3_POOL, "pool size");
+static_assert(kP3Slots.peak[1] == P3_POOL_128 && kP3Slots.top[1] < P3_POOL_128 && kP3Slots.top[0] < P3_POOL_128,
+              "pool size, m <= 128");
 __device__ const P3SlotPack p3_slot_pack = kP3Slots;
 
 // Slot of tile (I, k); tab is this lane's dword of the packed table (I, k uniform).
@@ -220,7 +235,8 @@ __device__ inline int p3_slot(uint32_t tab, int I, int k) {
 // L_Ip^T = Y C_Ip^T for one tile I > p, in place in the pool (the wavefront
 // reads the whole tile before it writes it) and to global memory
 // (device-coherent stores: a concurrent TRSM reads them).
-__device__ inline void p3_solve_tile(P3Smem& sm, const double* Y, double* Mw, int ldi, uint32_t tab, int I, int p,
+template <int NPOOL>
+__device__ inline void p3_solve_tile(P3SmemT<NPOOL>& sm, const double* Y, double* Mw, int ldi, uint32_t tab, int I, int p,
                                      int lane, int li, int lk) {
     double* X = sm.pool[p3_slot(tab, I, p)];
     dbl4 o = {0.0, 0.0, 0.0, 0.0};
@@ -244,8 +260,8 @@ __device__ inline void p3_solve_tile(P3Smem& sm, const double* Y, double* Mw, in
 // pairs (a lone first panel when their count is odd), so the loop body is one
 // basic block; the owner of tile p+2 hands its diagonal block to wavefront 0
 // through Dn.
-template <int S0>
-__device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& sm, const double* Y, const double* Mc,
+template <int S0, int NPOOL>
+__device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3SmemT<NPOOL>& sm, const double* Y, const double* Mc,
                                                 double* Mw, int ldi, uint32_t tab, int w, int np, int p, int lane,
                                                 int li, int lk) {
     constexpr int NS = P3_SLOTS - S0;
@@ -356,8 +372,8 @@ __device__ __forceinline__ void p3_update_slots(dbl4 (&nxt)[P3_SLOTS], P3Smem& s
 }
 
 // p3_update_slots<s0> for a run-time s0 < P3_SLOTS.
-template <int S0 = 0>
-__device__ __forceinline__ void p3_update_dispatch(int s0, dbl4 (&nxt)[P3_SLOTS], P3Smem& sm, const double* Y,
+template <int S0 = 0, int NPOOL>
+__device__ __forceinline__ void p3_update_dispatch(int s0, dbl4 (&nxt)[P3_SLOTS], P3SmemT<NPOOL>& sm, const double* Y,
                                                    const double* Mc, double* Mw, int ldi, uint32_t tab, int w, int np,
                                                    int p, int lane, int li, int lk) {
     if constexpr (S0 == P3_SLOTS - 1) {
@@ -403,7 +419,8 @@ __device__ __forceinline__ void p3_update_dispatch(int s0, dbl4 (&nxt)[P3_SLOTS]
 // Every tile of L stays in the LDS pool from its reduction to its last use,
 // so global memory is read only for the raw tiles, each once.  The chain of
 // diagonal factorizations overlaps all the other work.
-__device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3Smem& sm, int* fail_out, double* ls_out,
+template <int NPOOL>
+__device__ inline void potrf3(double* M, int64_t ld, int m, double* Yd, P3SmemT<NPOOL>& sm, int* fail_out, double* ls_out,
                               double* lc_out, int* fpo) {
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63, li = lane & 15, lk = lane >> 4;

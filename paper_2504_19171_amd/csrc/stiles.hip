@@ -667,17 +667,20 @@ __device__ inline bool col_update(const UpBlock& u, const int* ftr, int np, cons
 // launch cannot deadlock, however many workgroups are resident): 0 is the
 // POTRF of L_JJ, then the TRSM row blocks (tile J+1 first), then the update
 // blocks.  The factorization of the next tile column is the next launch.
-union ColSmem {
-    P3Smem po;
+template <int NPOOL>
+union ColSmemT {
+    P3SmemT<NPOOL> po;
     TrSmem tr;
 };
+using ColSmem = ColSmemT<P3_POOL>;
 // Task t of tile column J; false when the kernel must stop (a wait failed).
 // upd (single-launch factor, else nullptr): the POTRF waits until the
 // earlier columns' updates of its tile are in, a TRSM block until those of
 // its rows are; the update blocks wait for the earlier updates of their
 // targets (col_update).  gt: the task's ticket in the launch (the test hook
 // Sched::withhold names one whose signals are never sent).
-__device__ inline bool col_task(ColSmem& sm, int& sh, double* Lm, const Lay& L, int64_t J, double* Yd, int* cf,
+template <int NPOOL>
+__device__ inline bool col_task(ColSmemT<NPOOL>& sm, int& sh, double* Lm, const Lay& L, int64_t J, double* Yd, int* cf,
                                 const Sched& st, double* ldp, int* info, int t, int* upd, int gt) {
     const int ntr = col_tr_blocks(L, J);
     const int nbr = L.b / 16, s = L.s(J), C64 = L.b / 64;
@@ -1470,6 +1473,7 @@ __global__ __launch_bounds__(NT) void kb_factor_setup(const BInst* bi) {
 // tasks come first), i.e. task 0 (the POTRFs) of every matrix first, then
 // task 1 of every matrix, and so on.  Each matrix's tasks keep their order, so
 // every task waits only for smaller tickets.
+#define KB_COL_WG_PER_CU 2   // workgroups per compute unit of kb_column at tiles <= 128 (registers: 252 VGPRs)
 struct BColArgs {
     const BInst* bi;
     const int* off;      // [T + 1], off[T] = ntot
@@ -1480,8 +1484,13 @@ struct BColArgs {
     int* err;            // the batch's error word
     int64_t spin_limit;
 };
+// NPOOL = P3_POOL_128 when every tile of the batch is at most 128 wide: the
+// smaller LDS footprint (49 KB against 147 KB) lets two workgroups share a
+// compute unit, so the many small TRSM and update tasks of a column run twice
+// as wide.
+template <int NPOOL>
 __global__ __launch_bounds__(P3_NT) void kb_column(BColArgs a, int64_t J) {
-    __shared__ ColSmem sm;
+    __shared__ ColSmemT<NPOOL> sm;
     __shared__ int sh;
     Sched sc;
     sc.ticket = a.ticket;
@@ -2518,10 +2527,18 @@ static int factor_batched_impl(const stiles_batch_item* items, int32_t count, vo
         tm_end(tm, STILES_TK_OTHER, st);
     }
     LAUNCH(STILES_TK_OTHER, kb_factor_setup, dim3(count), dim3(NT), 0, st, dbi);
+    int maxb = 0;
+    for (int k = 0; k < count; ++k) maxb = std::max(maxb, bi[k].L.b);
     for (int64_t J = 0; J < pl.maxN; ++J) {
         const ColQ& q = cq[J];
         const BColArgs a{dbi, dint + q.off_at, dint + q.order_at, q.T, q.ntot, dint + tick_at + J, dint + err_at, spin};
-        LAUNCH(STILES_TK_FACTOR, kb_column, dim3((unsigned)std::min(q.ntot, di.cus)), dim3(P3_NT), 0, st, a, J);
+        if (maxb <= 128) {
+            LAUNCH(STILES_TK_FACTOR, kb_column<P3_POOL_128>, dim3((unsigned)std::min(q.ntot, KB_COL_WG_PER_CU * di.cus)),
+                   dim3(P3_NT), 0, st, a, J);
+        } else {
+            LAUNCH(STILES_TK_FACTOR, kb_column<P3_POOL>, dim3((unsigned)std::min(q.ntot, di.cus)), dim3(P3_NT), 0, st,
+                   a, J);
+        }
     }
     {
         const BArgs a{dbi, dseg + zu_at, zu_n, spin};
