@@ -890,26 +890,36 @@ __global__ __launch_bounds__(NT) void k_trmm_all(const double* Lm, double* W, La
 
 // Phase 2 initial value of each diagonal tile, "LAUUM": Sigma_JJ = X_J^T X_J
 // (and the corner Sigma_AA = X_A^T X_A, which is final).  Lower 64 x 64
-// blocks, mirrored so the tiles are full symmetric.
+// blocks, mirrored so the tiles are full symmetric.  Blocks are numbered
+// densely: lauum_per(L) per band tile column, then the corner's
+// (lauum_corner(L), none without an arrow).
 __host__ __device__ inline int lauum_per(const Lay& L) {
-    const int nb64 = L.b / 64, nab = arrow_blocks(L.ap);
-    return std::max(nb64 * (nb64 + 1) / 2, nab * (nab + 1) / 2);
-}
-__device__ inline void lauum_body(const double* W, double* S, const Lay& L, int bid, double* smem) {
     const int nb64 = L.b / 64;
+    return nb64 * (nb64 + 1) / 2;
+}
+__host__ __device__ inline int lauum_corner(const Lay& L) {
     const int nab = arrow_blocks(L.ap);
+    return L.ap > 0 ? nab * (nab + 1) / 2 : 0;
+}
+// blocks of tile columns j0.. and the corner
+__host__ __device__ inline int64_t lauum_blocks(const Lay& L, int64_t j0) {
+    return (L.nt - j0) * (int64_t)lauum_per(L) + lauum_corner(L);
+}
+__device__ inline void lauum_body(const double* W, double* S, const Lay& L, int64_t bid, double* smem) {
     const int per = lauum_per(L);
-    const int64_t J = bid / per;
-    const int t = bid % per;
+    const int64_t nband = L.nt * (int64_t)per;
     const double* X;
     double* O;
     int m;
     int64_t ld;
-    if (J < L.nt) {
-        if (t >= nb64 * (nb64 + 1) / 2) return;
+    int t;
+    if (bid < nband) {
+        const int64_t J = bid / per;
+        t = (int)(bid % per);
         X = W + L.band(J, 0); O = S + L.band(J, 0); m = L.b; ld = L.b;
     } else {
-        if (t >= nab * (nab + 1) / 2) return;
+        t = (int)(bid - nband);
+        if (t >= lauum_corner(L)) return;
         X = W + L.corner(); O = S + L.corner(); m = L.ap; ld = L.ap;
     }
     int rb, cb;
@@ -925,7 +935,7 @@ __device__ inline void lauum_body(const double* W, double* S, const Lay& L, int 
 }
 __global__ __launch_bounds__(NT) void k_lauum_all(const double* W, double* S, Lay L, int64_t j0) {
     __shared__ double smem[GB_SMEM_DOUBLES];
-    lauum_body(W, S, L, xcd_block((int)blockIdx.x, (int)gridDim.x) + (int)(j0 * lauum_per(L)), smem);
+    lauum_body(W, S, L, xcd_block((int)blockIdx.x, (int)gridDim.x) + j0 * lauum_per(L), smem);
 }
 
 #define ARW (-1)   // "the arrow" in place of a band tile offset
@@ -1448,11 +1458,10 @@ __device__ inline int bseg_find(const BSeg* seg, int nseg, int b) {
     const int bid = b_ - (a).seg[q_].first;                                    \
     const int nblk = (a).seg[q_ + 1].first - (a).seg[q_].first;                \
     (void)nblk
-// ... of this workgroup
+// ... of this workgroup.  (The XCD grouping of the single-matrix Phase 1
+// products, applied to the batched ones, made them slower: kb_lauum 597 ->
+// 762 us per pass; not used here.)
 #define BATCH_DECODE(a, I, bid, nblk) BATCH_DECODE_AT(a, I, bid, nblk, (int)blockIdx.x)
-// ... of this workgroup's XCD-grouped number (blocks that share operands on one L2)
-#define BATCH_DECODE_XCD(a, I, bid, nblk) \
-    BATCH_DECODE_AT(a, I, bid, nblk, xcd_block((int)blockIdx.x, (int)gridDim.x))
 
 // Factor set-up of every matrix (one workgroup per matrix): info and error
 // words, tile column counters.
@@ -1557,13 +1566,13 @@ __global__ __launch_bounds__(NT) void kb_trtri(BArgs a) {
 
 __global__ __launch_bounds__(NT) void kb_trmm(BArgs a) {
     __shared__ double smem[GB_SMEM_DOUBLES];
-    BATCH_DECODE_XCD(a, I, bid, nblk);
+    BATCH_DECODE(a, I, bid, nblk);
     trmm_body(I.Lm, selinv_ws(I.L, I.ws).W, I.L, bid, smem);
 }
 
 __global__ __launch_bounds__(NT) void kb_lauum(BArgs a) {
     __shared__ double smem[GB_SMEM_DOUBLES];
-    BATCH_DECODE_XCD(a, I, bid, nblk);
+    BATCH_DECODE(a, I, bid, nblk);
     lauum_body(selinv_ws(I.L, I.ws).W, I.S, I.L, bid, smem);
 }
 
@@ -1686,19 +1695,20 @@ __global__ __launch_bounds__(NT) void k_gather(const double* S, Lay L, const int
 __global__ __launch_bounds__(NT) void k_inv_lauum(const double* W, double* D, int64_t ldd, Lay L) {
     __shared__ double smem[GB_SMEM_DOUBLES];
     const int per = lauum_per(L);
-    const int64_t J = blockIdx.x / per;
-    const int t = blockIdx.x % per;
-    const int nb64 = L.b / 64, nab = arrow_blocks(L.ap);
+    const int64_t nband = L.nt * (int64_t)per;
     const double* X;
     double* O;
     int m;
     int64_t ld;
-    if (J < L.nt) {
-        if (t >= nb64 * (nb64 + 1) / 2) return;
+    int t;
+    if ((int64_t)blockIdx.x < nband) {
+        const int64_t J = blockIdx.x / per;
+        t = (int)(blockIdx.x % per);
         X = W + L.band(J, 0); m = L.b; ld = L.b;
         O = D + J * L.b + J * L.b * ldd;
     } else {
-        if (t >= nab * (nab + 1) / 2) return;
+        t = (int)(blockIdx.x - nband);
+        if (t >= lauum_corner(L)) return;
         X = W + L.corner(); m = L.ap; ld = L.ap;
         const int64_t o = L.nt * (int64_t)L.b;
         O = D + o + o * ldd;
@@ -2191,7 +2201,7 @@ static int selinv_impl(const double* Lm, double* S, const stiles_layout& lay, in
         }
     }
     {
-        const int64_t g = (L.nt - j1 + (L.ap > 0)) * (int64_t)lauum_per(L);
+        const int64_t g = lauum_blocks(L, j1);
         LAUNCH(STILES_TK_PHASE1, k_lauum_all, dim3((unsigned)g), dim3(NT), 0, st, (const double*)v.W, S, L, j1);
     }
     // Phase 2, bottom-right to top-left, one persistent launch
@@ -2330,7 +2340,7 @@ int stiles_inverse(const double* Lm, double* Ainv, int64_t n, int64_t bandwidth,
         const int64_t g = L.nt * (int64_t)(L.bt * nb64 + nab) * nb64;
         if (g > 0) LAUNCH(STILES_TK_PHASE1, k_trmm_all, dim3((unsigned)g), dim3(NT), 0, st, Lm, v.W, L, (int64_t)0);
     }
-    LAUNCH(STILES_TK_PHASE1, k_inv_lauum, dim3((unsigned)((L.nt + (L.ap > 0)) * (int64_t)lauum_per(L))), dim3(NT), 0,
+    LAUNCH(STILES_TK_PHASE1, k_inv_lauum, dim3((unsigned)lauum_blocks(L, 0)), dim3(NT), 0,
            st, (const double*)v.W, D, np, L);
     for (int64_t J = L.nt - 1; J >= 0; --J) {
         const int64_t rows = np - (J + 1) * L.b;
@@ -2608,7 +2618,7 @@ static int selinv_batched_impl(const stiles_batch_item* items, int32_t count, vo
     }
     close(tm);
     t.start(segs.size());
-    for (int k = 0; k < count; ++k) t.add(segs, k, (int)((bi[k].L.nt + (bi[k].L.ap > 0)) * (int64_t)lauum_per(bi[k].L)));
+    for (int k = 0; k < count; ++k) t.add(segs, k, (int)lauum_blocks(bi[k].L, 0));
     close(la);
     // Phase 2: the resident workgroups shared in proportion to the task
     // counts, at least one per matrix
