@@ -1464,7 +1464,7 @@ __device__ inline int bseg_find(const BSeg* seg, int nseg, int b) {
 #define BATCH_DECODE(a, I, bid, nblk) BATCH_DECODE_AT(a, I, bid, nblk, (int)blockIdx.x)
 
 // Factor set-up of every matrix (one workgroup per matrix): info and error
-// words, tile column counters.
+// words, tile column counters and update counters (contiguous).
 __global__ __launch_bounds__(NT) void kb_factor_setup(const BInst* bi) {
     const BInst& I = bi[blockIdx.x];
     const FactorWs f = factor_ws(I.L, I.ws);
@@ -1472,25 +1472,32 @@ __global__ __launch_bounds__(NT) void kb_factor_setup(const BInst* bi) {
         *f.winfo = 0x7fffffff;
         *f.err = 0;
     }
-    const int64_t n = I.L.nt * (int64_t)col_stride(I.L);
+    const int64_t n = I.L.nt * (int64_t)col_stride(I.L) + upd_ints(I.L);
     for (int64_t i = threadIdx.x; i < n; i += NT) f.cf[i] = 0;
 }
 
-// Tile column J of every matrix with N > J in one launch, all its tasks on
-// one ticket queue: ticket g is local task t of matrix order[g - off[t]]
-// (the matrices sorted by decreasing task count, so those with more than t
-// tasks come first), i.e. task 0 (the POTRFs) of every matrix first, then
-// task 1 of every matrix, and so on.  Each matrix's tasks keep their order, so
-// every task waits only for smaller tickets.
+// Tile columns J0 .. J0 + ncol - 1 of every matrix (those with N > J) in one
+// launch, all their tasks on one ticket queue, column after column.  Inside
+// column c, ticket tb[c] + g is local task t of matrix order[g - off[t]] (the
+// matrices sorted by decreasing task count, so those with more than t tasks
+// come first), i.e. task 0 (the POTRFs) of every matrix first, then task 1 of
+// every matrix, and so on.  Each matrix's tasks keep their order, and the
+// tasks of a column wait for the earlier columns' updates of their tiles
+// through the per-block update counters (as in k_factor_all), so every task
+// waits only for smaller tickets: the POTRF of column J0 + 1 starts as soon as
+// column J0's updates of its tile are in, while the rest of column J0 goes on.
 #define KB_COL_WG_PER_CU 2   // workgroups per compute unit of kb_column at tiles <= 128 (registers: 252 VGPRs)
+#define KB_COL_MAX 16        // tile columns per kb_column launch, at most
 struct BColArgs {
     const BInst* bi;
-    const int* off;      // [T + 1], off[T] = ntot
-    const int* order;
-    int T;
-    int ntot;
+    const int* ints;                 // the queue tables
+    int ncol;
+    int tb[KB_COL_MAX + 1];          // first ticket of each column; tb[ncol]: all
+    int off_at[KB_COL_MAX];          // ints + off_at[c]: off of column c, [T[c] + 1]
+    int order_at[KB_COL_MAX];        // ints + order_at[c]: its matrices, by decreasing task count
+    int T[KB_COL_MAX];               // most tasks of one matrix in column c
     int* ticket;
-    int* err;            // the batch's error word
+    int* err;                        // the batch's error word
     int64_t spin_limit;
 };
 // NPOOL = P3_POOL_128 when every tile of the batch is at most 128 wide: the
@@ -1498,7 +1505,7 @@ struct BColArgs {
 // compute unit, so the many small TRSM and update tasks of a column run twice
 // as wide.
 template <int NPOOL>
-__global__ __launch_bounds__(P3_NT) void kb_column(BColArgs a, int64_t J) {
+__global__ __launch_bounds__(P3_NT) void kb_column(BColArgs a, int64_t J0) {
     __shared__ ColSmemT<NPOOL> sm;
     __shared__ int sh;
     Sched sc;
@@ -1507,18 +1514,23 @@ __global__ __launch_bounds__(P3_NT) void kb_column(BColArgs a, int64_t J) {
     sc.spin_limit = a.spin_limit;
     sc.withhold = -1;
     for (;;) {
-        const int g = sched_next(sc, a.ntot, &sh);
+        const int g = sched_next(sc, a.tb[a.ncol], &sh);
         if (g < 0) return;
-        int lo = 0, hi = a.T;
+        int c = 0;
+        while (c + 1 < a.ncol && g >= a.tb[c + 1]) ++c;
+        const int gl = g - a.tb[c];
+        const int* off = a.ints + a.off_at[c];
+        int lo = 0, hi = a.T[c];
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (a.off[mid] <= g) lo = mid; else hi = mid;
+            if (off[mid] <= gl) lo = mid; else hi = mid;
         }
         const int t = lo;
-        const BInst& I = a.bi[a.order[g - a.off[t]]];
+        const BInst& I = a.bi[a.ints[a.order_at[c] + gl - off[t]]];
+        const int64_t J = J0 + c;
         const FactorWs f = factor_ws(I.L, I.ws);
         if (!col_task(sm, sh, I.Lm, I.L, J, f.Yd + J * (int64_t)I.L.b * 16, f.cf + J * col_stride(I.L), sc,
-                      f.ldp + 2 * J, f.winfo, t, nullptr, g))
+                      f.ldp + 2 * J, f.winfo, t, f.upd, g))
             return;
     }
 }
@@ -1904,6 +1916,20 @@ static int64_t spin_limit_ticks(const DevInfo& di) {
         if (v > 0) ms = v;
     }
     return (int64_t)(ms * (double)di.clock_khz);
+}
+
+// Tile columns per batched column launch: STILES_KB_COLS (1 .. KB_COL_MAX),
+// default 8.  Measured on 64 matrices at tile 64: batched factor 64.4 / 55.6 /
+// 52.1 / 49.9 / 49.1 ms at 1 / 2 / 4 / 8 / 16 columns per launch; served
+// capacity (three concurrent lanes) 130 / 131 / 131 / 120 jobs/s at 1 / 4 / 8
+// / 16, as a launch that holds every compute unit longer leaves the other
+// lanes less room.
+static int kb_cols_per_launch() {
+    if (const char* e = getenv("STILES_KB_COLS")) {
+        const int v = atoi(e);
+        if (v >= 1 && v <= KB_COL_MAX) return v;
+    }
+    return 8;
 }
 
 static int debug_withhold() {
@@ -2539,15 +2565,30 @@ static int factor_batched_impl(const stiles_batch_item* items, int32_t count, vo
     LAUNCH(STILES_TK_OTHER, kb_factor_setup, dim3(count), dim3(NT), 0, st, dbi);
     int maxb = 0;
     for (int k = 0; k < count; ++k) maxb = std::max(maxb, bi[k].L.b);
-    for (int64_t J = 0; J < pl.maxN; ++J) {
-        const ColQ& q = cq[J];
-        const BColArgs a{dbi, dint + q.off_at, dint + q.order_at, q.T, q.ntot, dint + tick_at + J, dint + err_at, spin};
+    const int cols = kb_cols_per_launch();
+    for (int64_t J0 = 0; J0 < pl.maxN; J0 += cols) {
+        BColArgs a;
+        memset(&a, 0, sizeof(a));
+        a.bi = dbi;
+        a.ints = dint;
+        a.ncol = (int)std::min<int64_t>(cols, pl.maxN - J0);
+        for (int c = 0; c < a.ncol; ++c) {
+            const ColQ& q = cq[J0 + c];
+            a.off_at[c] = (int)q.off_at;
+            a.order_at[c] = (int)q.order_at;
+            a.T[c] = q.T;
+            a.tb[c + 1] = a.tb[c] + q.ntot;
+        }
+        a.ticket = dint + tick_at + J0;
+        a.err = dint + err_at;
+        a.spin_limit = spin;
+        const int ntot = a.tb[a.ncol];
         if (maxb <= 128) {
-            LAUNCH(STILES_TK_FACTOR, kb_column<P3_POOL_128>, dim3((unsigned)std::min(q.ntot, KB_COL_WG_PER_CU * di.cus)),
-                   dim3(P3_NT), 0, st, a, J);
+            LAUNCH(STILES_TK_FACTOR, kb_column<P3_POOL_128>, dim3((unsigned)std::min(ntot, KB_COL_WG_PER_CU * di.cus)),
+                   dim3(P3_NT), 0, st, a, J0);
         } else {
-            LAUNCH(STILES_TK_FACTOR, kb_column<P3_POOL>, dim3((unsigned)std::min(q.ntot, di.cus)), dim3(P3_NT), 0, st,
-                   a, J);
+            LAUNCH(STILES_TK_FACTOR, kb_column<P3_POOL>, dim3((unsigned)std::min(ntot, di.cus)), dim3(P3_NT), 0, st, a,
+                   J0);
         }
     }
     {
