@@ -26,12 +26,12 @@ PEAK_F64_TFLOPS = 78.6    # MI355X dense FP64 (matrix and vector)
 # WRITE_SIZE runs scaled by a copy of known size (profiles/k_factor_all_large_hbm_traffic.md),
 # valid only for the kernel sources they were taken with (sha256 prefix of csrc/*)
 # and the workload named.
-MEASURED_TRAFFIC = {("factor", "large"): {"bytes_per_launch": 13.137e9, "sources": "3cce3117795851b3"}}
+MEASURED_TRAFFIC = {("factor", "large"): {"bytes_per_launch": 13.133e9, "sources": "a0004f271920e463"}}
 # FP64 matrix-core counters of the same launch (SQ_INSTS_VALU_MFMA_MOPS_F64 x 512 flops and
 # SQ_VALU_MFMA_BUSY_CYCLES over GRBM_GUI_ACTIVE x SIMDs; profiles/mfma_f64_large_counters.md),
 # valid for the kernel sources they were taken with.
 MEASURED_MFMA = {("factor", "large"): {"mfma_flops_per_launch": 2.034e11, "mfma_busy": 0.075,
-                                        "sources": "3cce3117795851b3"}}
+                                        "sources": "a0004f271920e463"}}
 
 
 def sources_hash() -> str:

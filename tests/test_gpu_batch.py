@@ -88,6 +88,24 @@ def test_batched_equals_single_bitwise(mix_run, torch_cuda):
         assert r["ld"][k] == float(ld.item()), k
 
 
+@pytest.mark.parametrize("cols", ["1", "3", "16"])
+def test_columns_per_launch_bitwise(mix_run, torch_cuda, monkeypatch, cols):
+    """The batched factor launches several tile columns at a time (STILES_KB_COLS,
+    default 8), the columns of one launch chained through per-block update
+    counters.  Every count gives the same L and log det, bit for bit, as the
+    default run (and so as the single-matrix calls)."""
+    torch = torch_cuda
+    from paper_2504_19171_amd import stiles as st
+    monkeypatch.setenv("STILES_KB_COLS", cols)
+    print(f"batched factor, {cols} tile columns per launch", flush=True)
+    Ls, ld, info = st.factor_batched(mix_run["As"], mix_run["lays"])
+    torch.cuda.synchronize()
+    assert (info.cpu().numpy()[:, 0] == 0).all(), cols
+    for k in range(len(MIX)):
+        assert torch.equal(Ls[k], mix_run["Ls"][k]), (cols, k, MIX[k])
+    assert np.array_equal(ld.cpu().numpy(), mix_run["ld"]), cols
+
+
 def test_batched_matches_oracle(mix_run, oracle_mod):
     from gpu_util import factor_error, sigma_error, logdet_error, SIGMA_TOL, LOGDET_TOL, L_TOL
     r = mix_run
