@@ -147,9 +147,12 @@ int stiles_selinv(const double* L, double* Sigma, int64_t n, int64_t bandwidth, 
  * fills the device.  The tasks and their arithmetic are those of stiles_factor
  * and stiles_selinv on each matrix alone: results are identical bit for bit.
  *
- * The tile-column launches run in step across the batch (launch J covers
- * column J of every matrix with N > J), so the batch takes about as long as
- * its longest matrix, and a batch with one tile size runs best.
+ * The factor's launches run in step across the batch: each covers eight
+ * consecutive tile columns of every matrix that has them (the environment
+ * variable STILES_KB_COLS, 1 to 16, sets the count; the columns of a launch
+ * are chained through per-block update counters), so the batch takes about as
+ * long as its longest matrix, and a batch with one tile size runs best.  With
+ * every tile at most 128 wide, the factor runs two workgroups per compute unit.
  *
  * items (host array of `count` entries, read during the call only):
  *   n, bandwidth, arrow, tile   as for stiles_layout_init; reserved must be 0
@@ -162,9 +165,11 @@ int stiles_selinv(const double* L, double* Sigma, int64_t n, int64_t bandwidth, 
  *           stiles_selinv's info
  * workspace  device, at least stiles_batch_workspace_bytes(items, count); one
  *           workspace serves both calls (contents on entry are ignored).
- * The calls copy a small table of the matrices from host memory into the
- * workspace with hipMemcpyAsync on `stream`; as the source is pageable memory,
- * that copy may wait for work already queued on the stream.
+ * The calls copy a small table of the matrices into the workspace with
+ * hipMemcpyAsync on `stream`, staged in pinned host memory that the library
+ * owns (up to 16 buffers, kept until the process ends; a buffer is reused
+ * once its copy has completed, and when all are busy the call waits for one).
+ * The call returns without waiting for the copy itself.
  * Returns 0; -1 if items is NULL or an item is invalid (its layout, a NULL
  * pointer, reserved != 0, or for the selinv Sigma NULL or equal to L); -2 if
  * count < 1; -3 / -4 for the workspace and its size; STILES_EHIP.
@@ -194,9 +199,9 @@ int stiles_selinv_batched(const stiles_batch_item* items, int32_t count, void* w
 /*
  * The batched calls in two parts, for replay from a HIP graph (the batching
  * of the method's calls, as above): stiles_batch_upload copies the tables of
- * both calls for these items into their two areas of the workspace (from
- * pageable host memory, stream-ordered, like the calls above; items need
- * Sigma set); the _enqueue variants then only enqueue device work (kernels
+ * both calls for these items into their two areas of the workspace (staged
+ * and stream-ordered like the calls above; items need Sigma set); the
+ * _enqueue variants then only enqueue device work (kernels
  * and, where A != L, device-to-device copies) that reads those tables and
  * restarts every counter it uses, so a stream capture of them can be
  * replayed any number of times.  Each _enqueue call must be given the same
